@@ -1,0 +1,109 @@
+"""Learned precision indicator (oracle): features, MLP forward/backward, Adam, BF16.
+
+The paper lets the detection argument of eq. lambda_1_i be replaced by another
+criterion (Appendix B, the remark after eq. lambda_1_i; Sec. II B).  The learned
+criterion is a fully connected network 4-64-64-64-1 with tanh hidden units and a
+linear output:
+    h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), h3 = tanh(W3 h2 + b3), y = W4 h3 + b4
+on standardised per-atom inputs x = (f - mu) / sigma, f = [rho_EAM, min(CSP, 50),
+coordination (neighbours closer than 3.08 A), |F_EAM|].  Its target is
+log(|F_ACE - F_EAM| + 1e-3) and the loss is the mean squared error over a batch.
+Adam: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + 1e-8).
+BF16 inference: weights and every layer input rounded to bfloat16 (nearest-even),
+products summed in float32, tanh in float32.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .geometry import displacements, sq_dist
+
+LAYERS = (4, 64, 64, 64, 1)
+COORD_R = 3.08
+CSP_CAP = 50.0
+
+
+def features(pos, lo, hi, periodic, csr, rho, csp, f_eam):
+    """[n, 4] float64 features (f_eam is the unweighted EAM force [3, n])."""
+    n = pos.shape[1]
+    box = np.asarray(hi) - np.asarray(lo)
+    offsets, idx = csr
+    i = np.repeat(np.arange(n), np.diff(offsets))
+    dx, dy, dz = displacements(pos, box, periodic, i, idx)
+    close = sq_dist(dx, dy, dz) < COORD_R * COORD_R
+    coord = np.bincount(i[close], minlength=n).astype(np.float64)
+    fn = np.sqrt((f_eam * f_eam).sum(axis=0))
+    return np.stack([rho, np.minimum(csp, CSP_CAP), coord, fn], axis=1)
+
+
+def init_params(seed: int):
+    """Glorot-uniform weights (as inputs; drawn in layer order), zero biases."""
+    rng = np.random.default_rng(seed)
+    ps = []
+    for a, b in zip(LAYERS[:-1], LAYERS[1:]):
+        lim = np.sqrt(6.0 / (a + b))
+        ps.append(rng.uniform(-lim, lim, size=(b, a)))
+        ps.append(np.zeros(b))
+    return ps
+
+
+def forward(params, x):
+    """Returns (y [n], cache)."""
+    acts = [x]
+    h = x
+    for k in range(3):
+        h = np.tanh(h @ params[2 * k].T + params[2 * k + 1])
+        acts.append(h)
+    y = (h @ params[6].T + params[7])[:, 0]
+    return y, acts
+
+
+def loss_and_grad(params, x, target):
+    """Mean squared error and its gradient with respect to every parameter."""
+    y, acts = forward(params, x)
+    nb = x.shape[0]
+    r = y - target
+    loss = float((r * r).mean())
+    g = [None] * 8
+    dy = (2.0 / nb) * r[:, None]  # [n, 1]
+    g[6] = dy.T @ acts[3]
+    g[7] = dy.sum(axis=0)
+    delta = dy @ params[6]  # [n, 64]
+    for k in (2, 1, 0):
+        dz = delta * (1.0 - acts[k + 1] ** 2)
+        g[2 * k] = dz.T @ acts[k]
+        g[2 * k + 1] = dz.sum(axis=0)
+        delta = dz @ params[2 * k]
+    return loss, g
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (t counts from 1); updates params, m, v in place."""
+    for k in range(len(params)):
+        m[k] = b1 * m[k] + (1.0 - b1) * grads[k]
+        v[k] = b2 * v[k] + (1.0 - b2) * grads[k] * grads[k]
+        mh = m[k] / (1.0 - b1 ** t)
+        vh = v[k] / (1.0 - b2 ** t)
+        params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def to_bf16(a):
+    """Round float32 values to the nearest bfloat16 (ties to even), returned as float32."""
+    a = np.asarray(a, dtype=np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32)
+    return np.where(np.isnan(a), a, out)
+
+
+def forward_bf16(params, x):
+    """Inference with bf16 weights/activations and float32 sums."""
+    h = to_bf16(x)
+    for k in range(3):
+        W = to_bf16(params[2 * k]).astype(np.float32)
+        h = np.tanh((h.astype(np.float32) @ W.T + np.float32(params[2 * k + 1])).astype(np.float32))
+        h = to_bf16(h)
+    W = to_bf16(params[6]).astype(np.float32)
+    return (h.astype(np.float32) @ W.T + np.float32(params[7]))[:, 0].astype(np.float32)

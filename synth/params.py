@@ -1,0 +1,106 @@
+"""Parameters of the synthetic potentials and of the precision criterion (inputs only).
+
+The EAM amplitudes below are chosen so that the perfect FCC lattice at
+``a = 3.615`` Angstrom is stress-free; that property is checked by the oracle tests,
+not computed here.  The random ACE parameters are plain normal draws in a fixed order
+(radial mixing ``W``, then ``c1``, then ``c2``).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .systems import A_CU
+
+
+@dataclasses.dataclass(frozen=True)
+class EamParams:
+    """Closed-form EAM: phi(r)=A exp(-alpha(r-r0)) psi((r-rc)/h),
+    rho(r)=exp(-beta(r-r0)) psi((r-rc)/h), F(rho)=-sqrt(rho)."""
+
+    A: float
+    alpha: float
+    beta: float
+    r0: float
+    rc: float = 5.0
+    h: float = 0.5
+
+
+@dataclasses.dataclass(frozen=True)
+class AceParams:
+    """Synthetic ACE: Chebyshev radial basis of ``n_max`` functions mixed by ``W``
+    (shape ``[l_max+1, n_max, n_max]``), real spherical harmonics up to ``l_max``,
+    coefficient vectors ``c1``/``c2`` over the product basis, optional EAM anchor."""
+
+    n_max: int
+    l_max: int
+    W: np.ndarray
+    c1: np.ndarray
+    c2: np.ndarray
+    rc: float = 5.0
+    h: float = 0.5
+    s_a: float = 6.0
+    eps: float = 0.1
+    anchor: EamParams | None = None
+
+
+@dataclasses.dataclass(frozen=True)
+class PrecisionParams:
+    """Detection and switching parameters.
+
+    ``switch_kind`` 0: w0 = clamp((CSP-lo)/(hi-lo), 0, 1); 1: w0 = 1 - f_cut((CSP-lo)/(hi-lo)).
+    ``r_hi`` = 0 disables spreading.  ``n_nn`` nearest neighbours (``+ n_buffer``) enter
+    the centro-symmetry parameter; neighbours are taken within ``r_cut``.
+    """
+
+    csp_lo: float
+    csp_hi: float
+    switch_kind: int
+    r_lo: float = 0.0
+    r_hi: float = 0.0
+    n_nn: int = 12
+    n_buffer: int = 0
+    r_cut: float = 5.0
+
+
+def eam_cu_like(a: float = A_CU) -> EamParams:
+    """The fast potential: alpha 4.3/A, beta 1.8/A, r0 = a/sqrt(2), stress-free at ``a``."""
+    return EamParams(A=0.1464436514321396, alpha=4.3, beta=1.8, r0=a / np.sqrt(2.0))
+
+
+def eam_anchor(a: float = A_CU) -> EamParams:
+    """The EAM-like part folded into the anchored ACE (alpha 4.4, beta 1.75, stress-free)."""
+    return EamParams(A=0.14169266975963063, alpha=4.4, beta=1.75, r0=a / np.sqrt(2.0))
+
+
+def ace_random(n_max: int, l_max: int, n_basis: int, seed: int,
+               anchored: bool = False, coef_std: float = 0.01) -> AceParams:
+    """Random-initialised ACE parameters.
+
+    Draw order from ``default_rng(seed)``: W ~ N(0, 1/n_max) of shape
+    ``[l_max+1, n_max, n_max]`` (index ``[l, n, k]``), then ``c1`` and ``c2`` ~ N(0, coef_std)
+    of length ``n_basis`` (the size of the product basis, supplied by the caller).
+    """
+    rng = np.random.default_rng(seed)
+    W = rng.normal(0.0, 1.0 / np.sqrt(n_max), size=(l_max + 1, n_max, n_max))
+    c1 = rng.normal(0.0, coef_std, size=n_basis)
+    c2 = rng.normal(0.0, coef_std, size=n_basis)
+    return AceParams(n_max=n_max, l_max=l_max, W=W, c1=c1, c2=c2,
+                     anchor=eam_anchor() if anchored else None)
+
+
+def precision_cfg0() -> PrecisionParams:
+    """Linear switch 0.2-0.5 A^2, no spreading."""
+    return PrecisionParams(csp_lo=0.2, csp_hi=0.5, switch_kind=0)
+
+
+def precision_hyb1() -> PrecisionParams:
+    """The paper's Hyb1 set: CSP 2.5/3.0 A^2, f_cut switch, spreading radii 4/12 A."""
+    return PrecisionParams(csp_lo=2.5, csp_hi=3.0, switch_kind=1, r_lo=4.0, r_hi=12.0)
+
+
+def precision_static() -> PrecisionParams:
+    """Hyb1 thresholds with shorter spreading radii 4/8 A (for small periodic boxes)."""
+    return PrecisionParams(csp_lo=2.5, csp_hi=3.0, switch_kind=1, r_lo=4.0, r_hi=8.0)
