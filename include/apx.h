@@ -1,0 +1,232 @@
+/*
+ * apx.h -- C ABI of the MI355X (gfx950) adaptive-precision EAM-ACE force library.
+ *
+ * The library evaluates, on one GPU, the per-step force routine of the
+ * adaptive-precision potential of Immel, Drautz and Sutmann (arXiv:2411.03002):
+ * neighbour lists, centro-symmetry detection and switching weights, classical EAM
+ * for every atom, the atomic cluster expansion (ACE) only where the precise weight is
+ * non-zero, the site-weighted blend, and velocity-Verlet integration.
+ *
+ * Conventions for every entry point:
+ *  - Return value: apx_status, APX_OK (0) on success, a negative code otherwise.
+ *    Nothing throws across the ABI and nothing aborts; apx_last_error() returns the
+ *    message of the last failure on that context.
+ *  - Array arguments are caller-owned DEVICE pointers unless marked "host".  The
+ *    library never frees caller memory.  Arrays of vectors use structure-of-arrays
+ *    layout [3][n]: x components at [0, n), y at [n, 2n), z at [2n, 3n).
+ *  - Work is enqueued on the context's HIP stream and the call returns at once.
+ *    Only calls that return a host scalar synchronise; each says "(sync)".
+ *  - A context is not thread-safe: use one per host thread.
+ *  - Weights: w is the weight of the precise potential (ACE).  The paper's switching
+ *    parameter is the weight of the fast potential, lambda = 1 - w.
+ *  - Periodic coordinates must lie in [lo, hi); coordinates in a non-periodic
+ *    dimension must lie in [lo, hi) as well (APX_EINVAL otherwise, reported by the
+ *    neighbour build).
+ */
+#ifndef APX_H
+#define APX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apx_status;
+#define APX_OK 0
+#define APX_EINVAL (-1)     /* bad argument: null pointer, size mismatch, unsupported size */
+#define APX_ENOMEM (-2)     /* device allocation failed */
+#define APX_EDEVICE (-3)    /* a HIP runtime call failed */
+#define APX_ECAPACITY (-4)  /* a caller buffer is too small; the needed size is returned */
+#define APX_ENONFINITE (-5) /* a non-finite value where a finite one is required */
+
+#define APX_FP64 0
+#define APX_FP32 1
+
+typedef struct apx_ctx apx_ctx;
+typedef struct apx_ace_model apx_ace_model;
+typedef struct apx_md apx_md;
+
+/* ------------------------------------------------------------------ context */
+/* Create a context on HIP device `device` enqueuing on `stream` (a hipStream_t; NULL
+ * means the null stream).  The context owns its scratch memory. */
+apx_status apx_ctx_create(int32_t device, void* stream, apx_ctx** out);
+apx_status apx_ctx_set_stream(apx_ctx* ctx, void* stream);
+void apx_ctx_destroy(apx_ctx* ctx);
+const char* apx_last_error(const apx_ctx* ctx);
+apx_status apx_ctx_synchronize(apx_ctx* ctx); /* (sync) */
+const char* apx_version(void);
+
+/* ------------------------------------------------------------------- atoms */
+typedef struct {
+  int64_t n;             /* number of atoms */
+  const double* pos;     /* device [3][n] positions, Angstrom */
+  double lo[3], hi[3];   /* box bounds */
+  int32_t periodic[3];   /* 1 = periodic along that axis */
+  const uint8_t* frozen; /* device [n] or NULL: 1 = never moved, w pinned to 0, no CSP */
+} apx_atoms;
+
+/* --------------------------------------------------------- neighbour lists */
+/* Full Verlet list in neighbour-major ELL layout: row i holds count[i] neighbours
+ * idx[k*n + i], k < count[i], in ascending j; every j != i whose minimum-image
+ * squared distance (dx*dx + dy*dy) + dz*dz is below r_list^2.  (The paper's force
+ * routine works on such lists, Sec. II D; the definition is the plain one.) */
+typedef struct {
+  int64_t n;      /* atoms the list was built for */
+  int32_t max_nb; /* row capacity, 1..128 */
+  int32_t* count; /* device [n] */
+  int32_t* idx;   /* device [max_nb][n] */
+  double r_list;  /* cutoff the list was built with (force cutoff + skin) */
+} apx_nlist;
+
+/* Build `nl` for `atoms` with cutoff `r_list`.  Periodic dimensions need
+ * r_list < L/2.  If some row needs more than nl->max_nb entries the call returns
+ * APX_ECAPACITY and stores the largest row length in *needed (host, required; (sync)).
+ * Rows are then truncated.  Otherwise *needed receives the largest row length. */
+apx_status apx_build_neighbors(apx_ctx* ctx, const apx_atoms* atoms, double r_list,
+                               apx_nlist* nl, int32_t* needed);
+
+/* ------------------------------------------------ detection and switching */
+/* CSP: Sec. II B eq. csp_1_i with Appendix A (LAMMPS definition with N + N_buffer
+ * candidates within r_cut, chosen by (squared distance, index); N/2 smallest pair
+ * values |r_a + r_b|^2 summed in ascending order; fewer candidates: +inf).
+ * w0: Appendix B eq. lambda_1_i read as the precise weight,
+ *     switch_kind 1: w0 = 1 - f_cut((CSP - csp_lo)/(csp_hi - csp_lo)),
+ *     switch_kind 0: w0 = clamp((CSP - csp_lo)/(csp_hi - csp_lo), 0, 1).
+ * Spreading: Appendix B eq. lambda_2_i, precise-weight form
+ *     w_i = max(w0_i, max_{j: r_ij < r_hi} w0_j f_cut((r_ij - r_lo)/(r_hi - r_lo)));
+ *     r_hi = 0 disables it (w = w0).
+ * f_cut: Appendix B, evaluated as ((1 - 1.875x) + 1.25x^3) - 0.375x^5 with
+ * x^3 = (x*x)*x, x^5 = x^3*(x*x), every operation rounded separately. */
+typedef struct {
+  int32_t n_nn;        /* N, even, 2..16 (12 for FCC) */
+  int32_t n_buffer;    /* N_buffer, N + N_buffer <= 16 */
+  int32_t switch_kind; /* 0 linear, 1 f_cut */
+  int32_t reserved;
+  double csp_lo, csp_hi; /* Angstrom^2 */
+  double r_cut;          /* CSP candidate cutoff, <= nl->r_list */
+  double r_lo, r_hi;     /* spreading radii, Angstrom */
+} apx_prec_params;
+
+/* Outputs (device, length n): csp, w0, w, mask (1 where w > 0); active receives the
+ * indices with w > 0 in ascending order and *n_active (host, (sync)) their number.
+ * w0_extra (device [n] or NULL) is an additional detection weight combined with the
+ * CSP-based w0 by max before spreading (used by the learned criterion). */
+apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                 const apx_prec_params* p, const double* w0_extra,
+                                 double* csp, double* w0, double* w, uint8_t* mask,
+                                 int32_t* active, int64_t* n_active);
+
+/* ------------------------------------------------------------------- EAM */
+/* Sec. III B eq. energy_eam: E_i = F(rho_i) + 1/2 sum_j phi(r_ij), rho_i = sum_j rho(r_ij)
+ * over r_ij < r_cut, with phi(r) = A exp(-alpha(r - r0)) psi((r - r_cut)/h),
+ * rho(r) = exp(-beta(r - r0)) psi((r - r_cut)/h), psi(x) = x^4/(1 + x^4) for x < 0
+ * else 0 (the taper of Appendix D), F(rho) = -sqrt(rho). */
+typedef struct {
+  double A, alpha, beta, r0, r_cut, h;
+} apx_eam_params;
+
+/* Outputs: e_site[n] = E_i^EAM (unweighted), rho[n], f[3][n] (overwritten) =
+ * -d/dx sum_k (1 - w_k) E_k^EAM (Appendix C eq. F_i_d, fast part).  w NULL means 0.
+ * rho may be NULL. */
+apx_status apx_eam_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                          const apx_eam_params* p, const double* w, double* e_site,
+                          double* rho, double* f);
+
+/* ------------------------------------------------------------------- ACE */
+/* Sec. III A: E_i = phi_i^(1) + sqrt(phi_i^(2)), phi^(p) = sum_v c_v^(p) B_iv, with the
+ * synthetic basis: radial g_k(r) = T_k(2r/r_cut - 1) psi((r - r_cut)/h), k < n_max;
+ * R_nl = sum_k W[l][n][k] g_k; real orthonormal Y_lm; A_nlm = (1/s_a) sum_j R_nl Y_lm;
+ * B1_n = A_n00; B2_(n1<=n2,l) = sum_m A_n1lm A_n2lm; B3 over (n,l) labels
+ * p = n(l_max+1) + l, p1 <= p2 <= p3, l1+l2+l3 even, triangle: sum G A A A with the
+ * real Gaunt coefficients.  Basis order: B1 (n), B2 (n1, n2, l), B3 (p1, p2, p3).
+ * sqrt is replaced by F_eps(x) = sign(x)(sqrt(|x| + eps^2) - eps).  If `anchored`, an
+ * EAM site energy with parameters `anchor` is added to E_i. */
+typedef struct {
+  int32_t n_max;    /* 1..12 */
+  int32_t l_max;    /* 3 or 4 */
+  double r_cut, h, s_a, eps;
+  const double* W;  /* host [l_max+1][n_max][n_max] */
+  const double* c1; /* host [n_basis] */
+  const double* c2; /* host [n_basis] */
+  int32_t anchored;
+  int32_t reserved;
+  apx_eam_params anchor;
+} apx_ace_desc;
+
+int64_t apx_ace_num_basis(int32_t n_max, int32_t l_max);
+/* Copies the descriptor's arrays to the device and builds the coupling tables. */
+apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* desc, apx_ace_model** out);
+void apx_ace_model_destroy(apx_ace_model* m);
+
+/* Evaluate ACE for the atoms listed in `active` (device, n_active entries, distinct).
+ * e_site[n] (overwritten): E_i^ACE at active atoms, 0 elsewhere.  f[3][n]
+ * (overwritten): -d/dx sum_{i active} w_i E_i^ACE (Appendix C eq. F_i_d, precise part);
+ * w NULL means 1.  dE_dc1/dE_dc2 (device [n_basis] or NULL, overwritten):
+ * d/dc of sum_i w_i E_i^ACE.  precision: APX_FP64, or APX_FP32 (basis, products and
+ * adjoint in float32 with compensated energy sums; forces accumulated in float64). */
+apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                 const apx_ace_model* m, const double* w,
+                                 const int32_t* active, int64_t n_active, int32_t precision,
+                                 double* e_site, double* f, double* dE_dc1, double* dE_dc2);
+
+/* ------------------------------------------------------------------ blend */
+/* Sec. II A eq. energy_hyb (precise-weight form): e_site = (1-w) e_eam + w e_ace (the ACE
+ * term only where w > 0); f = f_eam + f_ace; *e_pot (device scalar) = sum_i e_site,
+ * deterministic pairwise order. */
+apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const double* e_eam,
+                     const double* e_ace, const double* f_eam, const double* f_ace,
+                     double* e_site, double* f, double* e_pot);
+
+/* ---------------------------------------------------------- integration */
+#define APX_MODE_ADAPTIVE 0 /* EAM everywhere, ACE where w > 0, w from the criterion */
+#define APX_MODE_FULL_ACE 1 /* w = 1 for every mobile atom, no EAM, no detection */
+#define APX_MODE_EAM 2      /* w = 0, no ACE, no detection */
+
+typedef struct {
+  double dt;               /* ps */
+  double mass;             /* amu */
+  double skin;             /* neighbour skin, Angstrom; rebuild when an atom moved > skin/2 */
+  int32_t max_nb;          /* neighbour row capacity (<= 128) */
+  int32_t precision_every; /* recompute w every k steps (0: keep w) */
+  int32_t ace_precision;   /* APX_FP64 or APX_FP32 */
+  int32_t mode;            /* APX_MODE_* */
+  int32_t indenter;        /* 1: spherical indenter on */
+  int32_t reserved;
+  double ind_radius, ind_k;  /* R (A), K (eV/A^3): U = K/3 (R - d)^3, force K (R - d)^2 */
+  double ind_center[3];      /* centre at step 0 */
+  double ind_velocity[3];    /* A/ps */
+} apx_md_params;
+
+typedef struct {
+  int64_t steps;         /* steps taken by the call */
+  int64_t rebuilds;      /* neighbour rebuilds */
+  int64_t precision_updates;
+  int64_t n_active;      /* atoms with w > 0 after the call */
+  double e_pot, e_kin;   /* at the end of the call, eV (potential excludes the indenter) */
+  double e_indenter;     /* indenter energy at the end, eV */
+} apx_md_stats;
+
+/* An integrator bound to a box, potentials and criterion.  `atoms` supplies n, box,
+ * periodicity and the frozen mask (pos is ignored).  The ACE model and EAM parameters
+ * are referenced/copied; the model must outlive the integrator. */
+apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const apx_md_params* p,
+                         const apx_eam_params* eam, const apx_ace_model* ace,
+                         const apx_prec_params* prec, apx_md** out);
+void apx_md_destroy(apx_md* md);
+/* Neighbour list, weights (unless mode fixes them) and forces at the current
+ * positions: pos[3][n] (in), f[3][n] (out), w[n] (out). */
+apx_status apx_md_init(apx_md* md, const double* pos, double* f, double* w);
+/* Sec. II C eq. vv: n_steps velocity-Verlet steps with the weight update as step 2.
+ * pos, vel (A/ps), f, w are device arrays updated in place. stats: host, (sync). */
+apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, double* f, double* w,
+                           int64_t n_steps, apx_md_stats* stats);
+/* Device timers of the last apx_verlet_step call, milliseconds summed over its steps:
+ * out[0] half kick + drift + neighbour rebuilds, [1] weight updates, [2] EAM, [3] ACE,
+ * [4] blend + indenter + half kick. */
+apx_status apx_md_timings(apx_md* md, double* out5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APX_H */

@@ -1,0 +1,756 @@
+// Atomic cluster expansion on the active atoms: atomic base, product basis with energy
+// and adjoint, force scatter.
+//
+// Three kernels per evaluation (Sec. III A form E = phi1 + F_eps(phi2), basis defined in
+// the ABI header):
+//  1. k_ace_basis    one wave per active atom: per neighbour the Chebyshev radial values
+//                    and real solid harmonics, A'[k][lm] = sum_j g_k S_lm, then the radial
+//                    mixing A[n][lm] = sum_k Wp[l][n][k] A'[k][lm] (Wp folds W, N_l, 1/s_a).
+//  2. k_ace_products lane = atom, 64 (fp32) or 32 (fp64) atoms per block held in LDS,
+//                    8 waves splitting the coupling list.  B3 is evaluated by recoupling:
+//                    for a label pair (p1, p2) the coupled product
+//                    P_LM = sum G(l1 l2 L; m1 m2 M) A_p1m1 A_p2m2 is formed once and every
+//                    third block p3 >= p2 of degree L contributes B = sum_M P_LM A_p3M.
+//                    The adjoint pass reuses the same structure with
+//                    d = c1 + F_eps'(phi2) c2: Abar_p3 += d P, Pbar += d A_p3, then Pbar
+//                    is pushed back through the coupling into Abar_p1, Abar_p2.
+//  3. k_ace_force    one wave per active atom: back-projection of Abar through Wp, then
+//                    per neighbour the gradient of sum Abar'' g_k S_lm, scattered as
+//                    F_j -= w_i dE_i/dr_ij, F_i += w_i dE_i/dr_ij (float64 atomics).
+#include <cmath>
+
+#include "ace_coupling_gen.h"
+#include "ace_model.h"
+#include "device_util.h"
+
+namespace apx {
+
+struct AnchorDev {
+  double A, alpha, beta, r0, rc, inv_h, rc2;
+  int on;
+};
+
+template <class T>
+struct AceScratch {
+  T* A;             // [n_act][na]
+  T* Ab;            // [n_act][na]
+  double* e_anch;   // [n_act]
+  double* fp_anch;  // [n_act]
+};
+
+// ------------------------------------------------------------ shared helpers
+template <class T, int LMAX, bool GRAD>
+__device__ __forceinline__ void solid_harmonics(T x, T y, T z, T* S, T* Sx, T* Sy, T* Sz) {
+  S[0] = T(1);
+  if constexpr (GRAD) { Sx[0] = T(0); Sy[0] = T(0); Sz[0] = T(0); }
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    const T c = (l == 0) ? T(1) : T(sqrt((2.0 * l + 1.0) / (2.0 * l + 2.0)));
+    const int sll = l * l + 2 * l;  // (l, l)
+    const int slm = l * l;          // (l, -l)
+    const int tp = (l + 1) * (l + 1) + 2 * (l + 1);
+    const int bt = (l + 1) * (l + 1);
+    if (l == 0) {
+      S[tp] = c * x * S[sll];
+      S[bt] = c * y * S[sll];
+      if constexpr (GRAD) {
+        Sx[tp] = c * S[sll]; Sy[tp] = T(0); Sz[tp] = T(0);
+        Sx[bt] = T(0); Sy[bt] = c * S[sll]; Sz[bt] = T(0);
+      }
+    } else {
+      S[tp] = c * (x * S[sll] - y * S[slm]);
+      S[bt] = c * (y * S[sll] + x * S[slm]);
+      if constexpr (GRAD) {
+        Sx[tp] = c * (S[sll] + x * Sx[sll] - y * Sx[slm]);
+        Sy[tp] = c * (x * Sy[sll] - S[slm] - y * Sy[slm]);
+        Sz[tp] = c * (x * Sz[sll] - y * Sz[slm]);
+        Sx[bt] = c * (y * Sx[sll] + S[slm] + x * Sx[slm]);
+        Sy[bt] = c * (S[sll] + y * Sy[sll] + x * Sy[slm]);
+        Sz[bt] = c * (y * Sz[sll] + x * Sz[slm]);
+      }
+    }
+#pragma unroll
+    for (int m = -l; m <= l; ++m) {
+      const int dst = (l + 1) * (l + 1) + (l + 1) + m;
+      const int s1 = l * l + l + m;
+      const T a = T((2.0 * l + 1.0) / sqrt((l + m + 1.0) * (l - m + 1.0)));
+      if (m >= -(l - 1) && m <= l - 1) {
+        const int s2 = (l - 1) * (l - 1) + (l - 1) + m;
+        const T b = T(sqrt((l + m) * (l - m) * 1.0) / sqrt((l + m + 1.0) * (l - m + 1.0)));
+        S[dst] = a * z * S[s1] - b * S[s2];
+        if constexpr (GRAD) {
+          Sx[dst] = a * z * Sx[s1] - b * (T(2) * x * S[s2] + Sx[s2]);
+          Sy[dst] = a * z * Sy[s1] - b * (T(2) * y * S[s2] + Sy[s2]);
+          Sz[dst] = a * (S[s1] + z * Sz[s1]) - b * (T(2) * z * S[s2] + Sz[s2]);
+        }
+      } else {
+        S[dst] = a * z * S[s1];
+        if constexpr (GRAD) {
+          Sx[dst] = a * z * Sx[s1];
+          Sy[dst] = a * z * Sy[s1];
+          Sz[dst] = a * (S[s1] + z * Sz[s1]);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void taper_d(double x, double& p, double& dp) {
+  const double x2 = x * x;
+  const double x4 = x2 * x2;
+  const double den = 1.0 / (1.0 + x4);
+  p = x4 * den;
+  dp = 4.0 * x2 * x * den * den;
+}
+
+template <class T>
+__device__ __forceinline__ void taper_t(T x, T& p, T& dp) {
+  const T x2 = x * x;
+  const T x4 = x2 * x2;
+  const T den = T(1) / (T(1) + x4);
+  p = x4 * den;
+  dp = T(4) * x2 * x * den * den;
+}
+
+// ------------------------------------------------------------------ kernel 1
+template <class T, int LMAX>
+__global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos, int n, BoxDev b,
+                                                  const int* __restrict__ count, const int* __restrict__ idx,
+                                                  int max_nb, const int* __restrict__ active, int n_act,
+                                                  int K, T rc, T inv_h, double rc2, const T* __restrict__ Wp,
+                                                  AnchorDev an, AceScratch<T> sc) {
+  constexpr int LM = (LMAX + 1) * (LMAX + 1);
+  constexpr int kMaxK = 12;
+  extern __shared__ double smem_raw[];
+  T* gS = reinterpret_cast<T*>(smem_raw);  // [K][65]
+  T* sS = gS + kMaxK * 65;                 // [LM][65]
+  T* Ap = sS + LM * 65;                    // [K*LM]
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int i = active[q];
+  const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
+  int cnt = count[i];
+  if (cnt > max_nb) cnt = max_nb;
+  const int nout = K * LM;
+  T acc[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) acc[s] = T(0);
+  double rho_a = 0.0, pair_a = 0.0;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int k = c0 + lane;
+    T g[kMaxK];
+    T S[LM];
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) g[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < LM; ++a) S[a] = T(0);
+    if (k < cnt) {
+      const int j = idx[(size_t)k * n + i];
+      const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2) {
+        const double rd = sqrt(r2);
+        const T r = T(rd);
+        const T ir = T(1.0 / rd);
+        const T x = T(2) * r / rc - T(1);
+        T ps, dps;
+        taper_t<T>((r - rc) * inv_h, ps, dps);
+        T t0 = T(1), t1 = x;
+        g[0] = ps;
+        if (K > 1) g[1] = x * ps;
+#pragma unroll
+        for (int a = 2; a < kMaxK; ++a) {
+          const T t2 = T(2) * x * t1 - t0;
+          if (a < K) g[a] = t2 * ps;
+          t0 = t1;
+          t1 = t2;
+        }
+        solid_harmonics<T, LMAX, false>(T(dx) * ir, T(dy) * ir, T(dz) * ir, S, nullptr, nullptr, nullptr);
+      }
+      if (an.on && r2 < an.rc2) {
+        const double r = sqrt(r2);
+        double ps, dps;
+        taper_d((r - an.rc) * an.inv_h, ps, dps);
+        rho_a += exp(-an.beta * (r - an.r0)) * ps;
+        pair_a += exp(-an.alpha * (r - an.r0)) * ps;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a)
+      if (a < K) gS[a * 65 + lane] = g[a];
+#pragma unroll
+    for (int a = 0; a < LM; ++a) sS[a * 65 + lane] = S[a];
+    __syncthreads();
+    const int lim = (cnt - c0) < 64 ? (cnt - c0) : 64;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const int o = lane + 64 * s;
+      if (o < nout) {
+        const int kk = o / LM, lm = o - kk * LM;
+        T v = acc[s];
+        for (int nb = 0; nb < lim; ++nb) v += gS[kk * 65 + nb] * sS[lm * 65 + nb];
+        acc[s] = v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int o = lane + 64 * s;
+    if (o < nout) Ap[o] = acc[s];
+  }
+  __syncthreads();
+  const int na = K * LM;
+  T* Arow = sc.A + (size_t)q * na;
+  for (int o = lane; o < na; o += 64) {
+    const int nn = o / LM, lm = o - nn * LM;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    const T* w = Wp + ((size_t)l * K + nn) * K;
+    T v = T(0);
+    for (int kk = 0; kk < K; ++kk) v += w[kk] * Ap[kk * LM + lm];
+    Arow[o] = v;
+  }
+  if (an.on) {
+    rho_a = wave_sum(rho_a);
+    pair_a = wave_sum(pair_a);
+    if (lane == 0) {
+      const double sq = sqrt(rho_a);
+      sc.e_anch[q] = (rho_a > 0.0 ? -sq : 0.0) + 0.5 * an.A * pair_a;
+      sc.fp_anch[q] = rho_a > 0.0 ? -0.5 / sq : 0.0;
+    }
+  } else if (lane == 0) {
+    sc.e_anch[q] = 0.0;
+    sc.fp_anch[q] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ kernel 2
+template <class T>
+struct Acc {
+  T s1, s2, e1, e2;  // running sums and compensation terms
+};
+
+template <class T, bool COMP>
+__device__ __forceinline__ void acc_add(T& s, T& e, T c, T B) {
+  if constexpr (COMP) {
+    // TwoProduct (via fma) and TwoSum: the dot-product compensation of Ogita, Rump and
+    // Oishi (2005), accumulating the rounding errors separately
+    const T p = c * B;
+    const T pe = fma(c, B, -p);
+    const T sn = s + p;
+    const T bp = sn - s;
+    const T se = (s - (sn - bp)) + (p - bp);
+    s = sn;
+    e += se + pe;
+  } else {
+    s = fma(c, B, s);
+  }
+}
+
+template <class T, int TILE>
+__device__ __forceinline__ void lds_add(T* p, T v, bool on) {
+  if (on) atomicAdd(p, v);
+}
+
+template <class T, int LMAX, int TILE, bool COMP, int L1, int L2>
+__device__ __forceinline__ void pair_fwd(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
+                                         Acc<T>& acc) {
+  using C = Couple<LMAX, L1, L2>;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  constexpr int ST = TILE + 1;
+  const int o1 = rec[0], o2 = rec[1];
+  T a[2 * L1 + 1], bb[2 * L2 + 1], P[P2];
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) a[m] = As[(o1 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) bb[m] = As[(o2 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < P2; ++m) P[m] = T(0);
+  C::template fwd<T>(a, bb, P);
+#pragma unroll
+  for (int L = 0; L <= LMAX; ++L) {
+    if ((C::kMask >> L) & 1) {
+      const int q0 = rec[4 + L], q1 = rec[5 + L];
+      for (int q = q0; q < q1; ++q) {
+        const int o3 = tb.t_off[q];
+        T B = T(0);
+#pragma unroll
+        for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[L * L + mm], As[(o3 + mm) * ST + t], B);
+        acc_add<T, COMP>(acc.s1, acc.e1, tb.t_c1[q], B);
+        acc_add<T, COMP>(acc.s2, acc.e2, tb.t_c2[q], B);
+      }
+    }
+  }
+}
+
+template <class T, int LMAX, int TILE, bool DC, int L1, int L2>
+__device__ __forceinline__ void pair_bwd(const T* __restrict__ As, T* __restrict__ Ab, const int* rec,
+                                         const AceTables<T>& tb, int t, bool own, T fp, double wdc, double wfp,
+                                         double* dc1, double* dc2) {
+  using C = Couple<LMAX, L1, L2>;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  constexpr int ST = TILE + 1;
+  const int o1 = rec[0], o2 = rec[1];
+  T a[2 * L1 + 1], bb[2 * L2 + 1], P[P2], Pb[P2];
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) a[m] = As[(o1 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) bb[m] = As[(o2 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < P2; ++m) {
+    P[m] = T(0);
+    Pb[m] = T(0);
+  }
+  C::template fwd<T>(a, bb, P);
+#pragma unroll
+  for (int L = 0; L <= LMAX; ++L) {
+    if ((C::kMask >> L) & 1) {
+      const int q0 = rec[4 + L], q1 = rec[5 + L];
+      for (int q = q0; q < q1; ++q) {
+        const int o3 = tb.t_off[q];
+        const T c1 = tb.t_c1[q], c2 = tb.t_c2[q];
+        const T d = fma(fp, c2, c1);
+        T B = T(0);
+#pragma unroll
+        for (int mm = 0; mm < 2 * L + 1; ++mm) {
+          const T a3 = As[(o3 + mm) * ST + t];
+          Pb[L * L + mm] = fma(d, a3, Pb[L * L + mm]);
+          lds_add<T, TILE>(&Ab[(o3 + mm) * ST + t], d * P[L * L + mm], own);
+          if constexpr (DC) B = fma(P[L * L + mm], a3, B);
+        }
+        if constexpr (DC) {
+          double g1 = own ? wdc * (double)B : 0.0;
+          double g2 = own ? wfp * (double)B : 0.0;
+          g1 = wave_sum(g1);
+          g2 = wave_sum(g2);
+          if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&dc1[tb.t_v[q]], g1);
+            atomicAdd(&dc2[tb.t_v[q]], g2);
+          }
+        }
+      }
+    }
+  }
+  T ga[2 * L1 + 1], gb[2 * L2 + 1];
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) ga[m] = T(0);
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) gb[m] = T(0);
+  C::template bwd<T>(a, bb, Pb, ga, gb);
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) lds_add<T, TILE>(&Ab[(o1 + m) * ST + t], ga[m], own);
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) lds_add<T, TILE>(&Ab[(o2 + m) * ST + t], gb[m], own);
+}
+
+#define APX_PAIR_CASES_3(X) \
+  X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(2, 0) X(2, 1) X(2, 2) X(2, 3) X(3, 0) X(3, 1) X(3, 2) X(3, 3)
+#define APX_PAIR_CASES_4(X)                                                                                  \
+  X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 0) X(2, 1) X(2, 2) X(2, 3) \
+  X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(4, 0) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
+
+
+// B1 and B2 contributions (wave 0 of each block), energy and adjoint.
+template <class T, int TILE, bool COMP>
+__device__ __forceinline__ void low_order_fwd(const T* __restrict__ As, const AceTables<T>& tb, int nb1, int nb2,
+                                              int t, Acc<T>& acc) {
+  constexpr int ST = TILE + 1;
+  for (int e = 0; e < nb1; ++e) {
+    const T a = As[tb.b1_off[e] * ST + t];
+    acc_add<T, COMP>(acc.s1, acc.e1, tb.b1_c1[e], a);
+    acc_add<T, COMP>(acc.s2, acc.e2, tb.b1_c2[e], a);
+  }
+  for (int e = 0; e < nb2; ++e) {
+    const int o1 = tb.b2_off[3 * e], o2 = tb.b2_off[3 * e + 1], l = tb.b2_off[3 * e + 2];
+    T B = T(0);
+    for (int m = 0; m < 2 * l + 1; ++m) B = fma(As[(o1 + m) * ST + t], As[(o2 + m) * ST + t], B);
+    acc_add<T, COMP>(acc.s1, acc.e1, tb.b2_c1[e], B);
+    acc_add<T, COMP>(acc.s2, acc.e2, tb.b2_c2[e], B);
+  }
+}
+
+template <class T, int TILE, bool DC>
+__device__ __forceinline__ void low_order_bwd(const T* __restrict__ As, T* __restrict__ Ab, const AceTables<T>& tb,
+                                              int nb1, int nb2, int t, bool own, T fp, double wdc, double wfp,
+                                              double* dc1, double* dc2) {
+  constexpr int ST = TILE + 1;
+  for (int e = 0; e < nb1; ++e) {
+    const int o = tb.b1_off[e];
+    const T d = fma(fp, tb.b1_c2[e], tb.b1_c1[e]);
+    lds_add<T, TILE>(&Ab[o * ST + t], d, own);
+    if constexpr (DC) {
+      const double B = (double)As[o * ST + t];
+      double g1 = own ? wdc * B : 0.0, g2 = own ? wfp * B : 0.0;
+      g1 = wave_sum(g1);
+      g2 = wave_sum(g2);
+      if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&dc1[tb.b1_v[e]], g1);
+        atomicAdd(&dc2[tb.b1_v[e]], g2);
+      }
+    }
+  }
+  for (int e = 0; e < nb2; ++e) {
+    const int o1 = tb.b2_off[3 * e], o2 = tb.b2_off[3 * e + 1], l = tb.b2_off[3 * e + 2];
+    const T d = fma(fp, tb.b2_c2[e], tb.b2_c1[e]);
+    T B = T(0);
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
+      lds_add<T, TILE>(&Ab[(o1 + m) * ST + t], d * x2, own);
+      lds_add<T, TILE>(&Ab[(o2 + m) * ST + t], d * x1, own);
+      if constexpr (DC) B = fma(x1, x2, B);
+    }
+    if constexpr (DC) {
+      double g1 = own ? wdc * (double)B : 0.0, g2 = own ? wfp * (double)B : 0.0;
+      g1 = wave_sum(g1);
+      g2 = wave_sum(g2);
+      if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&dc1[tb.b2_v[e]], g1);
+        atomicAdd(&dc2[tb.b2_v[e]], g2);
+      }
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T feps(T x, T eps, T& dfdx) {
+  const T ax = x < T(0) ? -x : x;
+  const T s = sqrt(ax + eps * eps);
+  dfdx = T(0.5) / s;
+  const T v = s - eps;
+  return x < T(0) ? -v : v;
+}
+
+template <class T, int LMAX, int TILE, bool COMP, bool DC>
+__global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __restrict__ Ag, T* __restrict__ Abg, int n_act,
+                                                                 int na, AceTables<T> tb, int nb1, int nb2, T eps,
+                                                                 const double* __restrict__ e_anch,
+                                                                 const int* __restrict__ active,
+                                                                 const double* __restrict__ w,
+                                                                 double* __restrict__ e_site,
+                                                                 double* __restrict__ dc1, double* __restrict__ dc2) {
+  constexpr int ST = TILE + 1;
+  extern __shared__ double smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* Ab = As + (size_t)na * ST;
+  T* red = Ab + (size_t)na * ST;        // [kAceWaves][4][TILE]
+  T* fps = red + kAceWaves * 4 * TILE;  // [TILE]
+  const int tid = threadIdx.x;
+  const int nthr = kAceWaves * 64;
+  const int q0 = blockIdx.x * TILE;
+  for (int e = tid; e < TILE * na; e += nthr) {
+    const int t = e / na, a = e - t * na;
+    const int q = q0 + t;
+    As[a * ST + t] = q < n_act ? Ag[(size_t)q * na + a] : T(0);
+    Ab[a * ST + t] = T(0);
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int t = lane % TILE;
+  const bool own = lane < TILE;
+  const int pb = __builtin_amdgcn_readfirstlane(tb.split[wv]);
+  const int pe = __builtin_amdgcn_readfirstlane(tb.split[wv + 1]);
+  // ------------------------------------------------------------ energy pass
+  Acc<T> acc{T(0), T(0), T(0), T(0)};
+  if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
+  for (int pi = pb; pi < pe; ++pi) {
+    const int* rec = tb.pairs + pi * kPairRec;
+    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+#define APX_FWD(A_, B_) \
+  case A_ * (LMAX + 1) + B_: pair_fwd<T, LMAX, TILE, COMP, A_, B_>(As, rec, tb, t, acc); break;
+    if constexpr (LMAX == 3) {
+      switch (type) { APX_PAIR_CASES_3(APX_FWD) default: break; }
+    } else {
+      switch (type) { APX_PAIR_CASES_4(APX_FWD) default: break; }
+    }
+#undef APX_FWD
+  }
+  if (own) {
+    red[(wv * 4 + 0) * TILE + t] = acc.s1;
+    red[(wv * 4 + 1) * TILE + t] = acc.e1;
+    red[(wv * 4 + 2) * TILE + t] = acc.s2;
+    red[(wv * 4 + 3) * TILE + t] = acc.e2;
+  }
+  __syncthreads();
+  if (wv == 0 && own) {
+    T s1 = T(0), e1 = T(0), s2 = T(0), e2 = T(0);
+    for (int v = 0; v < kAceWaves; ++v) {
+      acc_add<T, COMP>(s1, e1, T(1), red[(v * 4 + 0) * TILE + t]);
+      e1 += red[(v * 4 + 1) * TILE + t];
+      acc_add<T, COMP>(s2, e2, T(1), red[(v * 4 + 2) * TILE + t]);
+      e2 += red[(v * 4 + 3) * TILE + t];
+    }
+    const T phi1 = s1 + e1, phi2 = s2 + e2;
+    T dfdx;
+    const T f2 = feps<T>(phi2, eps, dfdx);
+    fps[t] = dfdx;
+    const int q = q0 + t;
+    if (q < n_act) e_site[active[q]] = (double)phi1 + (double)f2 + e_anch[q];
+  }
+  __syncthreads();
+  // ----------------------------------------------------------- adjoint pass
+  const T fp = fps[t];
+  double wdc = 0.0, wfp = 0.0;
+  if constexpr (DC) {
+    const int q = q0 + t;
+    if (q < n_act && own) {
+      wdc = w ? w[active[q]] : 1.0;
+      wfp = wdc * (double)fp;
+    }
+  }
+  if (wv == 0) low_order_bwd<T, TILE, DC>(As, Ab, tb, nb1, nb2, t, own, fp, wdc, wfp, dc1, dc2);
+  for (int pi = pb; pi < pe; ++pi) {
+    const int* rec = tb.pairs + pi * kPairRec;
+    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+#define APX_BWD(A_, B_)                                                                                   \
+  case A_ * (LMAX + 1) + B_:                                                                              \
+    pair_bwd<T, LMAX, TILE, DC, A_, B_>(As, Ab, rec, tb, t, own, fp, wdc, wfp, dc1, dc2);                 \
+    break;
+    if constexpr (LMAX == 3) {
+      switch (type) { APX_PAIR_CASES_3(APX_BWD) default: break; }
+    } else {
+      switch (type) { APX_PAIR_CASES_4(APX_BWD) default: break; }
+    }
+#undef APX_BWD
+  }
+  __syncthreads();
+  for (int e = tid; e < TILE * na; e += nthr) {
+    const int tt = e / na, a = e - tt * na;
+    const int q = q0 + tt;
+    if (q < n_act) Abg[(size_t)q * na + a] = Ab[a * ST + tt];
+  }
+}
+
+// ------------------------------------------------------------------ kernel 3
+template <class T, int LMAX>
+__global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos, int n, BoxDev b,
+                                                  const int* __restrict__ count, const int* __restrict__ idx,
+                                                  int max_nb, const int* __restrict__ active, int n_act, int K,
+                                                  T rc, T inv_h, double rc2, const T* __restrict__ Wp, AnchorDev an,
+                                                  AceScratch<T> sc, const double* __restrict__ w,
+                                                  double* __restrict__ f) {
+  constexpr int LM = (LMAX + 1) * (LMAX + 1);
+  constexpr int kMaxK = 12;
+  extern __shared__ double smem_raw[];
+  T* Ab2 = reinterpret_cast<T*>(smem_raw);  // [K][LM]
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int i = active[q];
+  const double wi = w ? w[i] : 1.0;
+  const T* Abr = sc.Ab + (size_t)q * K * LM;
+  // back-projection: Ab2[k][lm] = sum_n Wp[l][n][k] Abar[n][lm]
+  for (int o = lane; o < K * LM; o += 64) {
+    const int kk = o / LM, lm = o - kk * LM;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    T v = T(0);
+    for (int nn = 0; nn < K; ++nn) v += Wp[((size_t)l * K + nn) * K + kk] * Abr[nn * LM + lm];
+    Ab2[o] = v;
+  }
+  __syncthreads();
+  const double fpa = an.on ? sc.fp_anch[q] : 0.0;
+  const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
+  int cnt = count[i];
+  if (cnt > max_nb) cnt = max_nb;
+  double fix = 0.0, fiy = 0.0, fiz = 0.0;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int k = c0 + lane;
+    if (k < cnt) {
+      const int j = idx[(size_t)k * n + i];
+      const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      if (r2 < rc2) {
+        const double rd = sqrt(r2);
+        const T r = T(rd), ir = T(1.0 / rd);
+        const T ux = T(dx) * ir, uy = T(dy) * ir, uz = T(dz) * ir;
+        const T x = T(2) * r / rc - T(1);
+        const T dxdr = T(2) / rc;
+        T ps, dps;
+        taper_t<T>((r - rc) * inv_h, ps, dps);
+        dps *= inv_h;
+        T g[kMaxK], gd[kMaxK];
+        T t0 = T(1), t1 = x, d0 = T(0), d1 = T(1);
+        g[0] = ps;
+        gd[0] = dps;
+        g[1] = x * ps;
+        gd[1] = d1 * dxdr * ps + x * dps;
+#pragma unroll
+        for (int a = 2; a < kMaxK; ++a) {
+          const T t2 = T(2) * x * t1 - t0;
+          const T d2 = T(2) * t1 + T(2) * x * d1 - d0;
+          g[a] = t2 * ps;
+          gd[a] = d2 * dxdr * ps + t2 * dps;
+          t0 = t1;
+          t1 = t2;
+          d0 = d1;
+          d1 = d2;
+        }
+        T S[LM], Sx[LM], Sy[LM], Sz[LM];
+        solid_harmonics<T, LMAX, true>(ux, uy, uz, S, Sx, Sy, Sz);
+        T radial = T(0), vx = T(0), vy = T(0), vz = T(0);
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) {
+          int l = 0;
+          while ((l + 1) * (l + 1) <= lm) ++l;
+          T av = T(0), bv = T(0);
+          for (int kk = 0; kk < K; ++kk) {
+            const T c = Ab2[kk * LM + lm];
+            av = fma(c, g[kk], av);
+            bv = fma(c, gd[kk], bv);
+          }
+          radial += (bv - av * T(l) * ir) * S[lm];
+          const T ar = av * ir;
+          vx = fma(ar, Sx[lm], vx);
+          vy = fma(ar, Sy[lm], vy);
+          vz = fma(ar, Sz[lm], vz);
+        }
+        gx = (double)(radial * ux + vx);
+        gy = (double)(radial * uy + vy);
+        gz = (double)(radial * uz + vz);
+      }
+      if (an.on && r2 < an.rc2) {
+        const double r = sqrt(r2);
+        double ps, dps;
+        taper_d((r - an.rc) * an.inv_h, ps, dps);
+        dps *= an.inv_h;
+        const double eb = exp(-an.beta * (r - an.r0));
+        const double ea = exp(-an.alpha * (r - an.r0));
+        const double drho = eb * (dps - an.beta * ps);
+        const double dphi = an.A * ea * (dps - an.alpha * ps);
+        const double s = (fpa * drho + 0.5 * dphi) / r;
+        gx += s * dx;
+        gy += s * dy;
+        gz += s * dz;
+      }
+      gx *= wi;
+      gy *= wi;
+      gz *= wi;
+      if (gx != 0.0 || gy != 0.0 || gz != 0.0) {
+        unsafeAtomicAdd(&f[j], -gx);
+        unsafeAtomicAdd(&f[(size_t)n + j], -gy);
+        unsafeAtomicAdd(&f[2 * (size_t)n + j], -gz);
+      }
+      fix += gx;
+      fiy += gy;
+      fiz += gz;
+    }
+  }
+  fix = wave_sum(fix);
+  fiy = wave_sum(fiy);
+  fiz = wave_sum(fiz);
+  if (lane == 0) {
+    unsafeAtomicAdd(&f[i], fix);
+    unsafeAtomicAdd(&f[(size_t)n + i], fiy);
+    unsafeAtomicAdd(&f[2 * (size_t)n + i], fiz);
+  }
+}
+
+__global__ void k_fill_zero(double* __restrict__ p, long long m) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = 0.0;
+}
+
+template <class T, int LMAX>
+apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m,
+                   const AceTables<T>& tb, const double* w, const int* active, int n_act, double* e_site,
+                   double* f, double* dc1, double* dc2, apx::DevBuf& buf) {
+  constexpr int TILE = sizeof(T) == 4 ? 64 : 32;
+  constexpr int LM = (LMAX + 1) * (LMAX + 1);
+  const int n = (int)atoms->n;
+  const int na = m->na;
+  const size_t bytes_A = sizeof(T) * (size_t)n_act * na;
+  APX_ALLOC(ctx, buf, 2 * bytes_A + 2 * sizeof(double) * (size_t)n_act + 256);
+  AceScratch<T> sc;
+  sc.A = buf.as<T>();
+  sc.Ab = reinterpret_cast<T*>(reinterpret_cast<char*>(buf.p) + bytes_A);
+  sc.e_anch = reinterpret_cast<double*>(reinterpret_cast<char*>(buf.p) + 2 * bytes_A);
+  sc.fp_anch = sc.e_anch + n_act;
+  BoxDev b = make_box(atoms);
+  AnchorDev an{};
+  an.on = m->anchored;
+  if (an.on) {
+    an.A = m->anchor.A;
+    an.alpha = m->anchor.alpha;
+    an.beta = m->anchor.beta;
+    an.r0 = m->anchor.r0;
+    an.rc = m->anchor.r_cut;
+    an.inv_h = 1.0 / m->anchor.h;
+    an.rc2 = m->anchor.r_cut * m->anchor.r_cut;
+  }
+  const T rc = (T)m->r_cut, inv_h = (T)(1.0 / m->h);
+  const double rc2 = m->r_cut * m->r_cut;
+  const size_t lds1 = sizeof(T) * (12 * 65 + LM * 65 + 12 * LM);
+  k_ace_basis<T, LMAX><<<n_act, 64, lds1, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
+                                                         n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc);
+  APX_LAUNCH_CHECK(ctx);
+  const size_t lds2 = sizeof(T) * ((size_t)2 * na * (TILE + 1) + kAceWaves * 4 * TILE + TILE);
+  const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
+  if (dc1) {
+    auto kern = k_ace_products<T, LMAX, TILE, sizeof(T) == 4, true>;
+    APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    kern<<<nblk, kAceWaves * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                                      sc.e_anch, active, w, e_site, dc1, dc2);
+  } else {
+    auto kern = k_ace_products<T, LMAX, TILE, sizeof(T) == 4, false>;
+    APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    kern<<<nblk, kAceWaves * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                                      sc.e_anch, active, w, e_site, nullptr, nullptr);
+  }
+  APX_LAUNCH_CHECK(ctx);
+  const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
+  k_ace_force<T, LMAX><<<n_act, 64, lds3, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
+                                                         n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc, w, f);
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}
+
+}  // namespace apx
+
+using namespace apx;
+
+namespace {
+apx::DevBuf& ace_buffer(apx_ctx* ctx) { return ctx->ace_buf; }
+}  // namespace
+
+extern "C" apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                            const apx_ace_model* m, const double* w, const int32_t* active,
+                                            int64_t n_active, int32_t precision, double* e_site, double* f,
+                                            double* dE_dc1, double* dE_dc2) {
+  if (!ctx) return APX_EINVAL;
+  apx_status s = check_atoms(ctx, atoms);
+  if (s != APX_OK) return s;
+  if (!nl || !m) return fail(ctx, APX_EINVAL, "nl and model are required");
+  if (nl->n != atoms->n) return fail(ctx, APX_EINVAL, "nlist size mismatch");
+  if (m->r_cut > nl->r_list || (m->anchored && m->anchor.r_cut > nl->r_list))
+    return fail(ctx, APX_EINVAL, "ACE cutoff exceeds the neighbour-list cutoff");
+  if (precision != APX_FP64 && precision != APX_FP32) return fail(ctx, APX_EINVAL, "precision must be APX_FP64 or APX_FP32");
+  if (n_active < 0 || n_active > atoms->n) return fail(ctx, APX_EINVAL, "n_active out of range");
+  if ((dE_dc1 == nullptr) != (dE_dc2 == nullptr)) return fail(ctx, APX_EINVAL, "dE_dc1 and dE_dc2 go together");
+  const int n = (int)atoms->n;
+  if (n > 0 && (!e_site || !f)) return fail(ctx, APX_EINVAL, "e_site and f are required");
+  if (n_active > 0 && !active) return fail(ctx, APX_EINVAL, "active is NULL");
+  if (n > 0) {
+    k_fill_zero<<<blocks_for(3LL * n, 256), 256, 0, ctx->stream>>>(f, 3LL * n);
+    k_fill_zero<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(e_site, n);
+    APX_LAUNCH_CHECK(ctx);
+  }
+  if (dE_dc1) {
+    k_fill_zero<<<blocks_for(m->n_basis, 256), 256, 0, ctx->stream>>>(dE_dc1, m->n_basis);
+    k_fill_zero<<<blocks_for(m->n_basis, 256), 256, 0, ctx->stream>>>(dE_dc2, m->n_basis);
+    APX_LAUNCH_CHECK(ctx);
+  }
+  if (n_active == 0) return APX_OK;
+  const int na_ = (int)n_active;
+  if (precision == APX_FP64) {
+    if (m->l_max == 3) return ace_run<double, 3>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+    return ace_run<double, 4>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+  }
+  if (m->l_max == 3) return ace_run<float, 3>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+  return ace_run<float, 4>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+}

@@ -1,0 +1,230 @@
+// Host-side construction of the ACE coupling tables (basis catalogue, pair and triple
+// lists, per-wave work split) and their upload to the device.
+#include <cmath>
+#include <cstring>
+
+#include "ace_coupling_gen.h"
+#include "ace_model.h"
+
+namespace apx {
+namespace {
+
+template <int LMAX, int L1, int L2>
+constexpr int couple_terms() {
+  return Couple<LMAX, L1, L2>::kTerms;
+}
+
+template <int LMAX>
+int terms_of(int l1, int l2) {
+  static const int tab4[5][5] = {
+      {couple_terms<4, 0, 0>(), couple_terms<4, 0, 1>(), couple_terms<4, 0, 2>(), couple_terms<4, 0, 3>(), couple_terms<4, 0, 4>()},
+      {couple_terms<4, 1, 0>(), couple_terms<4, 1, 1>(), couple_terms<4, 1, 2>(), couple_terms<4, 1, 3>(), couple_terms<4, 1, 4>()},
+      {couple_terms<4, 2, 0>(), couple_terms<4, 2, 1>(), couple_terms<4, 2, 2>(), couple_terms<4, 2, 3>(), couple_terms<4, 2, 4>()},
+      {couple_terms<4, 3, 0>(), couple_terms<4, 3, 1>(), couple_terms<4, 3, 2>(), couple_terms<4, 3, 3>(), couple_terms<4, 3, 4>()},
+      {couple_terms<4, 4, 0>(), couple_terms<4, 4, 1>(), couple_terms<4, 4, 2>(), couple_terms<4, 4, 3>(), couple_terms<4, 4, 4>()}};
+  static const int tab3[4][4] = {
+      {couple_terms<3, 0, 0>(), couple_terms<3, 0, 1>(), couple_terms<3, 0, 2>(), couple_terms<3, 0, 3>()},
+      {couple_terms<3, 1, 0>(), couple_terms<3, 1, 1>(), couple_terms<3, 1, 2>(), couple_terms<3, 1, 3>()},
+      {couple_terms<3, 2, 0>(), couple_terms<3, 2, 1>(), couple_terms<3, 2, 2>(), couple_terms<3, 2, 3>()},
+      {couple_terms<3, 3, 0>(), couple_terms<3, 3, 1>(), couple_terms<3, 3, 2>(), couple_terms<3, 3, 3>()}};
+  return LMAX == 4 ? tab4[l1][l2] : tab3[l1][l2];
+}
+
+bool coupled(int l1, int l2, int l3) { return ((l1 + l2 + l3) % 2 == 0) && l3 >= std::abs(l1 - l2) && l3 <= l1 + l2; }
+
+struct Catalogue {
+  long long n_basis = 0;
+  std::vector<int> pairs, t_off, t_v, b1_off, b1_v, b2_off, b2_v, split;
+  std::vector<long long> t_coef, b1_coef, b2_coef;  // index into the user's coefficient vector
+};
+
+Catalogue build_catalogue(int n_max, int l_max) {
+  Catalogue c;
+  const int LL = l_max + 1;
+  const int P = n_max * LL;
+  auto off = [&](int p) { int n = p / LL, l = p % LL; return n * LL * LL + l * l; };
+  long long v = 0;
+  for (int n = 0; n < n_max; ++n) {
+    c.b1_off.push_back(n * LL * LL);
+    c.b1_v.push_back((int)v++);
+  }
+  for (int n1 = 0; n1 < n_max; ++n1)
+    for (int n2 = n1; n2 < n_max; ++n2)
+      for (int l = 0; l < LL; ++l) {
+        c.b2_off.push_back(n1 * LL * LL + l * l);
+        c.b2_off.push_back(n2 * LL * LL + l * l);
+        c.b2_off.push_back(l);
+        c.b2_v.push_back((int)v++);
+      }
+  // B3: enumerate in catalogue order to assign basis indices, then regroup per pair by L
+  std::vector<double> cost;
+  for (int p1 = 0; p1 < P; ++p1)
+    for (int p2 = p1; p2 < P; ++p2) {
+      const int l1 = p1 % LL, l2 = p2 % LL;
+      std::vector<std::vector<std::pair<int, int>>> byL(LL);  // (off3, v)
+      int found = 0;
+      for (int p3 = p2; p3 < P; ++p3) {
+        const int l3 = p3 % LL;
+        if (!coupled(l1, l2, l3)) continue;
+        byL[l3].push_back({off(p3), (int)v++});
+        ++found;
+      }
+      if (!found) continue;
+      int rec[kPairRec] = {0};
+      rec[0] = off(p1);
+      rec[1] = off(p2);
+      rec[2] = l1 * LL + l2;
+      double cst = 8.0 + (l_max == 4 ? terms_of<4>(l1, l2) : terms_of<3>(l1, l2));
+      int t = (int)c.t_off.size();
+      for (int L = 0; L < LL; ++L) {
+        rec[4 + L] = t;
+        for (auto& e : byL[L]) {
+          c.t_off.push_back(e.first);
+          c.t_v.push_back(e.second);
+          cst += 2 * L + 1 + 2;
+          ++t;
+        }
+      }
+      for (int L = LL; L < kPairRec - 4; ++L) rec[4 + L] = t;
+      c.pairs.insert(c.pairs.end(), rec, rec + kPairRec);
+      cost.push_back(cst);
+    }
+  c.n_basis = v;
+  // contiguous split of the pair list over the waves; wave 0 also owns B1 and B2
+  double b12 = (double)n_max;
+  for (size_t q = 0; q < c.b2_v.size(); ++q) b12 += 2 * c.b2_off[3 * q + 2] + 1 + 2;
+  double total = b12;
+  for (double x : cost) total += x;
+  const double target = total / kAceWaves;
+  c.split.assign(kAceWaves + 1, 0);
+  double acc = b12;
+  int w = 1;
+  const int np = (int)cost.size();
+  for (int q = 0; q < np && w < kAceWaves; ++q) {
+    acc += cost[q];
+    while (w < kAceWaves && acc >= w * target) c.split[w++] = q + 1;
+  }
+  while (w < kAceWaves) c.split[w++] = np;
+  c.split[kAceWaves] = np;
+  return c;
+}
+
+}  // namespace
+}  // namespace apx
+
+using namespace apx;
+
+extern "C" int64_t apx_ace_num_basis(int32_t n_max, int32_t l_max) {
+  if (n_max < 1 || n_max > 12 || (l_max != 3 && l_max != 4)) return -1;
+  return build_catalogue(n_max, l_max).n_basis;
+}
+
+template <class T>
+static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalogue& c, const double* c1,
+                       const double* c2, size_t* offs) {
+  const int LL = m->l_max + 1, nm = m->n_max;
+  // order: Wp, t_c1, t_c2, b1_c1, b1_c2, b2_c1, b2_c2
+  out.clear();
+  offs[0] = out.size();
+  for (int l = 0; l < LL; ++l) {
+    const double nl = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+    for (int n = 0; n < nm; ++n)
+      for (int k = 0; k < nm; ++k) out.push_back((T)(m->W[((size_t)l * nm + n) * nm + k] * nl / m->s_a));
+  }
+  offs[1] = out.size();
+  for (int v : c.t_v) out.push_back((T)c1[v]);
+  offs[2] = out.size();
+  for (int v : c.t_v) out.push_back((T)c2[v]);
+  offs[3] = out.size();
+  for (int v : c.b1_v) out.push_back((T)c1[v]);
+  offs[4] = out.size();
+  for (int v : c.b1_v) out.push_back((T)c2[v]);
+  offs[5] = out.size();
+  for (int v : c.b2_v) out.push_back((T)c1[v]);
+  offs[6] = out.size();
+  for (int v : c.b2_v) out.push_back((T)c2[v]);
+  offs[7] = out.size();
+}
+
+template <class T>
+static void set_tables(AceTables<T>& t, const T* base, const size_t* offs, const int* ib, const size_t* ioffs) {
+  t.Wp = base + offs[0];
+  t.t_c1 = base + offs[1];
+  t.t_c2 = base + offs[2];
+  t.b1_c1 = base + offs[3];
+  t.b1_c2 = base + offs[4];
+  t.b2_c1 = base + offs[5];
+  t.b2_c2 = base + offs[6];
+  t.pairs = ib + ioffs[0];
+  t.t_off = ib + ioffs[1];
+  t.t_v = ib + ioffs[2];
+  t.b1_off = ib + ioffs[3];
+  t.b1_v = ib + ioffs[4];
+  t.b2_off = ib + ioffs[5];
+  t.b2_v = ib + ioffs[6];
+  t.split = ib + ioffs[7];
+}
+
+extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, apx_ace_model** out) {
+  if (!ctx) return APX_EINVAL;
+  if (!d || !out) return fail(ctx, APX_EINVAL, "desc and out are required");
+  *out = nullptr;
+  if (d->n_max < 1 || d->n_max > 12) return fail(ctx, APX_EINVAL, "n_max must be in 1..12");
+  if (d->l_max != 3 && d->l_max != 4) return fail(ctx, APX_EINVAL, "l_max must be 3 or 4");
+  if (!d->W || !d->c1 || !d->c2) return fail(ctx, APX_EINVAL, "W, c1 and c2 are required");
+  if (!(d->r_cut > 0.0) || !(d->h > 0.0) || !(d->s_a > 0.0) || !(d->eps > 0.0))
+    return fail(ctx, APX_EINVAL, "r_cut, h, s_a and eps must be positive");
+  Catalogue c = build_catalogue(d->n_max, d->l_max);
+  apx_ace_model* m = new apx_ace_model();
+  m->device = ctx->device;
+  m->n_max = d->n_max;
+  m->l_max = d->l_max;
+  m->na = d->n_max * (d->l_max + 1) * (d->l_max + 1);
+  m->n_basis = c.n_basis;
+  m->npairs = (int)(c.pairs.size() / kPairRec);
+  m->ntrip = (int)c.t_off.size();
+  m->nb1 = (int)c.b1_v.size();
+  m->nb2 = (int)c.b2_v.size();
+  m->r_cut = d->r_cut;
+  m->h = d->h;
+  m->s_a = d->s_a;
+  m->eps = d->eps;
+  m->anchored = d->anchored ? 1 : 0;
+  m->anchor = d->anchor;
+  m->W.assign(d->W, d->W + (size_t)(d->l_max + 1) * d->n_max * d->n_max);
+  // integer tables
+  std::vector<int> ib;
+  size_t ioffs[8];
+  const std::vector<int>* parts[8] = {&c.pairs, &c.t_off, &c.t_v, &c.b1_off, &c.b1_v, &c.b2_off, &c.b2_v, &c.split};
+  for (int q = 0; q < 8; ++q) {
+    ioffs[q] = ib.size();
+    ib.insert(ib.end(), parts[q]->begin(), parts[q]->end());
+  }
+  std::vector<double> r64;
+  std::vector<float> r32;
+  size_t o64[8], o32[8];
+  fill_reals(r64, m, c, d->c1, d->c2, o64);
+  fill_reals(r32, m, c, d->c1, d->c2, o32);
+  if (m->ints.ensure(ib.size() * sizeof(int)) != hipSuccess || m->reals64.ensure(r64.size() * sizeof(double)) != hipSuccess ||
+      m->reals32.ensure(r32.size() * sizeof(float)) != hipSuccess) {
+    delete m;
+    return fail(ctx, APX_ENOMEM, "ACE table allocation failed");
+  }
+  hipError_t e1 = hipMemcpy(m->ints.p, ib.data(), ib.size() * sizeof(int), hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(m->reals64.p, r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice);
+  hipError_t e3 = hipMemcpy(m->reals32.p, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    delete m;
+    return fail(ctx, APX_EDEVICE, "ACE table upload failed");
+  }
+  set_tables(m->t64, m->reals64.as<double>(), o64, m->ints.as<int>(), ioffs);
+  set_tables(m->t32, m->reals32.as<float>(), o32, m->ints.as<int>(), ioffs);
+  *out = m;
+  return APX_OK;
+}
+
+extern "C" void apx_ace_model_destroy(apx_ace_model* m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  delete m;
+}

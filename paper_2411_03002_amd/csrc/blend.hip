@@ -1,0 +1,85 @@
+// Site-weighted blend of the two potentials and a deterministic energy reduction.
+//
+// Sec. II A eq. energy_hyb in the precise-weight form: E_i = (1 - w_i) E_i^EAM + w_i E_i^ACE,
+// the ACE term only where w_i > 0; forces are the sum of the two weighted parts
+// (Appendix C eq. F_i_d); E_pot = sum_i E_i.
+#include "common.h"
+#include "device_util.h"
+
+namespace apx {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedPer = 8;
+
+__global__ void __launch_bounds__(kRedThreads) k_blend(long long n, const double* __restrict__ w,
+                                                       const double* __restrict__ e_eam,
+                                                       const double* __restrict__ e_ace,
+                                                       const double* __restrict__ f_eam,
+                                                       const double* __restrict__ f_ace, double* __restrict__ e_site,
+                                                       double* __restrict__ f, double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  const long long base = (long long)blockIdx.x * kRedThreads * kRedPer;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kRedPer; ++k) {
+    const long long i = base + (long long)k * kRedThreads + threadIdx.x;
+    if (i < n) {
+      const double wi = w ? w[i] : 0.0;
+      double e = (1.0 - wi) * e_eam[i];
+      if (wi > 0.0) e += wi * e_ace[i];
+      e_site[i] = e;
+      s += e;
+      f[i] = f_eam[i] + f_ace[i];
+      f[n + i] = f_eam[n + i] + f_ace[n + i];
+      f[2 * n + i] = f_eam[2 * n + i] + f_ace[2 * n + i];
+    }
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Fixed-order pairwise sum of m partial values into *out (single block).
+__global__ void __launch_bounds__(kRedThreads) k_sum_partials(const double* __restrict__ partial, int m,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += kRedThreads) s += partial[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+}  // namespace apx
+
+using namespace apx;
+
+extern "C" apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const double* e_eam, const double* e_ace,
+                                const double* f_eam, const double* f_ace, double* e_site, double* f,
+                                double* e_pot) {
+  if (!ctx) return APX_EINVAL;
+  if (n < 0) return fail(ctx, APX_EINVAL, "negative size");
+  if (n > 0 && (!e_eam || !e_ace || !f_eam || !f_ace || !e_site || !f))
+    return fail(ctx, APX_EINVAL, "blend arrays are required");
+  if (!e_pot) return fail(ctx, APX_EINVAL, "e_pot is required");
+  const long long nb = n > 0 ? (n + kRedThreads * kRedPer - 1) / (kRedThreads * kRedPer) : 1;
+  APX_ALLOC(ctx, ctx->dtmp, sizeof(double) * (size_t)(nb + 1));
+  double* part = ctx->dtmp.as<double>();
+  if (n > 0) {
+    k_blend<<<(unsigned)nb, kRedThreads, 0, ctx->stream>>>(n, w, e_eam, e_ace, f_eam, f_ace, e_site, f, part);
+    APX_LAUNCH_CHECK(ctx);
+    k_sum_partials<<<1, kRedThreads, 0, ctx->stream>>>(part, (int)nb, e_pot);
+  } else {
+    k_sum_partials<<<1, kRedThreads, 0, ctx->stream>>>(part, 0, e_pot);
+  }
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}

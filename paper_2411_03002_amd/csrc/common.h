@@ -1,0 +1,101 @@
+// Internal definitions shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "apx.h"
+
+namespace apx {
+
+// Growable device allocation owned by a context or model.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b ? b : 16);
+    if (e == hipSuccess) bytes = b ? b : 16;
+    else p = nullptr;
+    return e;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Cell grid over the box: nc cells per axis of edge L/nc >= the requested size.
+struct Grid {
+  int nc[3];
+  int per[3];
+  double lo[3];
+  double L[3];
+  double inv_cell[3];
+  long long ncell() const { return (long long)nc[0] * nc[1] * nc[2]; }
+};
+
+}  // namespace apx
+
+struct apx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // scratch owned by the context
+  apx::DevBuf cell_id, cell_count, cell_start, cell_fill, cell_atoms;
+  apx::DevBuf scan_tmp, flags, itmp, itmp2, dtmp, ace_buf;
+  int* host_pinned = nullptr;  // small pinned staging area for readbacks
+};
+
+namespace apx {
+
+apx_status fail(apx_ctx* ctx, apx_status code, const char* fmt, ...);
+
+#define APX_HIP(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::apx::fail((ctx), APX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define APX_LAUNCH_CHECK(ctx) APX_HIP(ctx, hipGetLastError())
+
+#define APX_ALLOC(ctx, buf, bytes)                                                     \
+  do {                                                                                 \
+    if ((buf).ensure(bytes) != hipSuccess)                                             \
+      return ::apx::fail((ctx), APX_ENOMEM, "device allocation of %zu bytes failed",   \
+                         (size_t)(bytes));                                             \
+  } while (0)
+
+// Validates an apx_atoms descriptor.
+apx_status check_atoms(apx_ctx* ctx, const apx_atoms* a);
+
+// Grid with cells no smaller than `min_cell` (at least one cell per axis).
+Grid make_grid(const apx_atoms* a, double min_cell);
+
+// Bins atoms into the context's cell arrays (cell_start has ncell+1 entries).
+// Sets flags bit 0 on the device if a non-periodic coordinate lies outside the box.
+apx_status bin_atoms(apx_ctx* ctx, const apx_atoms* a, const Grid& g);
+
+// Exclusive scan of m int32 values `in` into `out` (m+1 entries, out[m] = total).
+apx_status scan_exclusive(apx_ctx* ctx, const int* in, long long m, int* out);
+
+// Reads `count` ints from device memory into host memory (synchronising).
+apx_status read_ints(apx_ctx* ctx, const int* dev, int* host, int count);
+
+inline unsigned int blocks_for(long long n, int threads) {
+  return (unsigned int)((n + threads - 1) / threads);
+}
+
+}  // namespace apx

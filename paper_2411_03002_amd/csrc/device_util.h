@@ -1,0 +1,84 @@
+// Device helpers: minimum image, exactly ordered squared distance, f_cut, reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace apx {
+
+constexpr int kWave = 64;
+
+// Minimum image of d = x_j - x_i along one axis of length L (both coordinates in
+// [lo, hi)): d -= L if d >= L/2; d += L if d < -L/2.
+__device__ __forceinline__ double min_image(double d, double L, double half, int periodic) {
+  if (periodic) {
+    if (d >= half) d -= L;
+    else if (d < -half) d += L;
+  }
+  return d;
+}
+
+// (dx*dx + dy*dy) + dz*dz with every product and sum rounded separately.
+__device__ __forceinline__ double sq_dist_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double a = dx * dx;
+  double b = dy * dy;
+  double c = dz * dz;
+  return (a + b) + c;
+}
+
+// f_cut of the paper (Appendix B), evaluated as ((1 - 1.875x) + 1.25x^3) - 0.375x^5 with
+// x^3 = (x*x)*x and x^5 = x^3*(x*x), no fused operations.
+__device__ __forceinline__ double fcut_exact(double x) {
+#pragma clang fp contract(off)
+  if (x < 0.0) return 1.0;
+  if (x > 1.0) return 0.0;
+  double x2 = x * x;
+  double x3 = x2 * x;
+  double x5 = x3 * x2;
+  double t1 = 1.875 * x;
+  double t3 = 1.25 * x3;
+  double t5 = 0.375 * x5;
+  return ((1.0 - t1) + t3) - t5;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Box lengths for minimum-image displacements.
+struct BoxDev {
+  double L[3], half[3];
+  int per[3];
+};
+
+inline BoxDev make_box(const apx_atoms* a) {
+  BoxDev b;
+  for (int d = 0; d < 3; ++d) {
+    b.L[d] = a->hi[d] - a->lo[d];
+    b.half[d] = 0.5 * b.L[d];
+    b.per[d] = a->periodic[d] ? 1 : 0;
+  }
+  return b;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double lo, double inv_cell, int nc) {
+  int c = (int)floor((x - lo) * inv_cell);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+}  // namespace apx

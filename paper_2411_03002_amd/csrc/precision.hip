@@ -1,0 +1,292 @@
+// Detection and switching: centro-symmetry parameter, initial weights, spreading,
+// mask and the ascending list of atoms that need the precise potential.
+#include <cmath>
+
+#include "common.h"
+#include "device_util.h"
+
+namespace apx {
+
+constexpr int kMaxM = 16;     // N + N_buffer
+constexpr int kMaxHalf = 8;   // N / 2
+
+struct PrecDev {
+  int n_nn, m, half, kind;
+  double csp_lo, width, rc2;
+};
+
+__device__ __forceinline__ double switch_w0(double c, const PrecDev& p) {
+#pragma clang fp contract(off)
+  double x = (c - p.csp_lo) / p.width;
+  if (p.kind == 0) return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+  return 1.0 - fcut_exact(x);
+}
+
+// One thread per atom.  Keeps the M nearest candidates within r_cut sorted by
+// (squared distance, index): the row is in ascending index, so a strict comparison
+// keeps the smaller index first among equal distances.
+__global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int n, Grid g,
+                                             const uint8_t* __restrict__ frozen,
+                                             const int* __restrict__ count, const int* __restrict__ idx,
+                                             int max_nb, PrecDev p, const double* __restrict__ w0_extra,
+                                             double* __restrict__ csp, double* __restrict__ w0,
+                                             double* __restrict__ w) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (frozen && frozen[i]) {
+    csp[i] = 0.0;
+    w0[i] = 0.0;
+    w[i] = 0.0;
+    return;
+  }
+  const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
+  const double hx = 0.5 * g.L[0], hy = 0.5 * g.L[1], hz = 0.5 * g.L[2];
+  double kr[kMaxM], kx[kMaxM], ky[kMaxM], kz[kMaxM];
+#pragma unroll
+  for (int a = 0; a < kMaxM; ++a) {
+    kr[a] = INFINITY;
+    kx[a] = ky[a] = kz[a] = 0.0;
+  }
+  int found = 0;
+  int cnt = count[i];
+  if (cnt > max_nb) cnt = max_nb;
+  for (int k = 0; k < cnt; ++k) {
+    const int j = idx[(size_t)k * n + i];
+    const double dx = min_image(pos[j] - xi, g.L[0], hx, g.per[0]);
+    const double dy = min_image(pos[(size_t)n + j] - yi, g.L[1], hy, g.per[1]);
+    const double dz = min_image(pos[2 * (size_t)n + j] - zi, g.L[2], hz, g.per[2]);
+    const double r2 = sq_dist_exact(dx, dy, dz);
+    if (!(r2 < p.rc2)) continue;
+    ++found;
+    if (!(r2 < kr[kMaxM - 1])) continue;
+    // insertion into the sorted arrays, unrolled so the arrays stay in registers
+    // once the new entry has been placed every later slot shifts by one, which keeps
+    // equal distances in arrival (ascending index) order
+    double cr = r2, cx = dx, cy = dy, cz = dz;
+    bool shifting = false;
+#pragma unroll
+    for (int a = 0; a < kMaxM; ++a) {
+      const bool take = shifting || cr < kr[a];
+      shifting = take;
+      const double tr = kr[a], tx = kx[a], ty = ky[a], tz = kz[a];
+      kr[a] = take ? cr : tr;
+      kx[a] = take ? cx : tx;
+      ky[a] = take ? cy : ty;
+      kz[a] = take ? cz : tz;
+      cr = take ? tr : cr;
+      cx = take ? tx : cx;
+      cy = take ? ty : cy;
+      cz = take ? tz : cz;
+    }
+  }
+  double c;
+  if (found < p.m) {
+    c = INFINITY;
+  } else {
+    double best[kMaxHalf];
+#pragma unroll
+    for (int a = 0; a < kMaxHalf; ++a) best[a] = INFINITY;
+#pragma unroll
+    for (int a = 0; a < kMaxM; ++a) {
+#pragma unroll
+      for (int b = a + 1; b < kMaxM; ++b) {
+        if (b < p.m) {
+          const double sx = kx[a] + kx[b], sy = ky[a] + ky[b], sz = kz[a] + kz[b];
+          double v = sq_dist_exact(sx, sy, sz);
+          bool shifting = false;
+#pragma unroll
+          for (int q = 0; q < kMaxHalf; ++q) {
+            const bool take = shifting || v < best[q];
+            shifting = take;
+            const double t = best[q];
+            best[q] = take ? v : t;
+            v = take ? t : v;
+          }
+        }
+      }
+    }
+    c = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxHalf; ++q)
+      if (q < p.half) c = c + best[q];
+  }
+  csp[i] = c;
+  double v0 = switch_w0(c, p);
+  if (w0_extra) {
+    const double e = w0_extra[i];
+    v0 = e > v0 ? e : v0;
+  }
+  w0[i] = v0;
+  w[i] = v0;
+}
+
+// Compacts the spreading sources (w0 > 0, not frozen) in any order.
+__global__ void k_sources(int n, const double* __restrict__ w0, const uint8_t* __restrict__ frozen,
+                          int* __restrict__ src, int* __restrict__ nsrc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (w0[i] > 0.0 && !(frozen && frozen[i])) src[atomicAdd(nsrc, 1)] = i;
+}
+
+struct SpreadDev {
+  double r_lo, width, rh2;
+  int reach[3];   // cells visited along each axis: offsets lo..lo+span-1
+  int span[3];
+};
+
+// One wave per source: lanes sweep the cells of the stencil, each lane one cell at a
+// time; every target within r_hi receives w0_j f_cut(...) by an atomic maximum on the
+// IEEE bit pattern (all candidates are > 0, where the unsigned order equals the
+// floating-point order), so the result does not depend on the visiting order.
+__global__ void __launch_bounds__(256) k_spread(const double* __restrict__ pos, int n, Grid g, SpreadDev s,
+                                                const int* __restrict__ src, int nsrc,
+                                                const double* __restrict__ w0, const uint8_t* __restrict__ frozen,
+                                                const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
+                                                unsigned long long* __restrict__ wbits) {
+#pragma clang fp contract(off)
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wid >= nsrc) return;
+  const int j = src[wid];
+  const double xj = pos[j], yj = pos[(size_t)n + j], zj = pos[2 * (size_t)n + j];
+  const double wj = w0[j];
+  const double hx = 0.5 * g.L[0], hy = 0.5 * g.L[1], hz = 0.5 * g.L[2];
+  const int cj0 = cell_coord(xj, g.lo[0], g.inv_cell[0], g.nc[0]);
+  const int cj1 = cell_coord(yj, g.lo[1], g.inv_cell[1], g.nc[1]);
+  const int cj2 = cell_coord(zj, g.lo[2], g.inv_cell[2], g.nc[2]);
+  const int total = s.span[0] * s.span[1] * s.span[2];
+  for (int q = lane; q < total; q += kWave) {
+    const int ox = q % s.span[0] + s.reach[0];
+    const int oy = (q / s.span[0]) % s.span[1] + s.reach[1];
+    const int oz = q / (s.span[0] * s.span[1]) + s.reach[2];
+    int cx = cj0 + ox, cy = cj1 + oy, cz = cj2 + oz;
+    if (g.per[0]) cx = ((cx % g.nc[0]) + g.nc[0]) % g.nc[0];
+    else if (cx < 0 || cx >= g.nc[0]) continue;
+    if (g.per[1]) cy = ((cy % g.nc[1]) + g.nc[1]) % g.nc[1];
+    else if (cy < 0 || cy >= g.nc[1]) continue;
+    if (g.per[2]) cz = ((cz % g.nc[2]) + g.nc[2]) % g.nc[2];
+    else if (cz < 0 || cz >= g.nc[2]) continue;
+    const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
+    const int b = cell_start[c], e = cell_start[c + 1];
+    for (int a = b; a < e; ++a) {
+      const int i = cell_atoms[a];
+      if (frozen && frozen[i]) continue;
+      const double dx = min_image(pos[i] - xj, g.L[0], hx, g.per[0]);
+      const double dy = min_image(pos[(size_t)n + i] - yj, g.L[1], hy, g.per[1]);
+      const double dz = min_image(pos[2 * (size_t)n + i] - zj, g.L[2], hz, g.per[2]);
+      const double r2 = sq_dist_exact(dx, dy, dz);
+      if (!(r2 < s.rh2)) continue;
+      const double r = sqrt(r2);
+      const double x = (r - s.r_lo) / s.width;
+      const double v = wj * fcut_exact(x);
+      if (v > 0.0) atomicMax(&wbits[i], (unsigned long long)__double_as_longlong(v));
+    }
+  }
+}
+
+__global__ void k_mask(int n, const double* __restrict__ w, uint8_t* __restrict__ mask, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = w[i] > 0.0 ? 1 : 0;
+  mask[i] = (uint8_t)m;
+  flag[i] = m;
+}
+
+__global__ void k_compact(int n, const int* __restrict__ flag, const int* __restrict__ pos_, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (flag[i]) out[pos_[i]] = i;
+}
+
+}  // namespace apx
+
+using namespace apx;
+
+// Spreading stencil: a cell edge no smaller than r_hi/3 (and the list cutoff), so that
+// three cells on each side cover r_hi; axes with fewer cells are visited once each.
+static void spread_stencil(const Grid& g, double r_hi, SpreadDev& s) {
+  for (int d = 0; d < 3; ++d) {
+    const double cell = g.L[d] / g.nc[d];
+    int reach = (int)std::ceil(r_hi / cell);
+    if (2 * reach + 1 >= g.nc[d] && g.per[d]) {
+      s.reach[d] = -(g.nc[d] / 2);
+      s.span[d] = g.nc[d];
+    } else {
+      s.reach[d] = -reach;
+      s.span[d] = 2 * reach + 1;
+    }
+  }
+}
+
+extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                            const apx_prec_params* p, const double* w0_extra, double* csp,
+                                            double* w0, double* w, uint8_t* mask, int32_t* active,
+                                            int64_t* n_active) {
+  if (!ctx) return APX_EINVAL;
+  apx_status s = check_atoms(ctx, atoms);
+  if (s != APX_OK) return s;
+  if (!nl || !p || !n_active) return fail(ctx, APX_EINVAL, "nl, params and n_active are required");
+  if (nl->n != atoms->n) return fail(ctx, APX_EINVAL, "nlist size mismatch");
+  const int n = (int)atoms->n;
+  if (n > 0 && (!csp || !w0 || !w || !mask || !active)) return fail(ctx, APX_EINVAL, "output arrays are NULL");
+  if (p->n_nn < 2 || (p->n_nn & 1) || p->n_buffer < 0 || p->n_nn + p->n_buffer > kMaxM)
+    return fail(ctx, APX_EINVAL, "n_nn must be even and n_nn + n_buffer <= %d", kMaxM);
+  if (!(p->csp_hi > p->csp_lo)) return fail(ctx, APX_EINVAL, "csp_hi must exceed csp_lo");
+  if (p->switch_kind != 0 && p->switch_kind != 1) return fail(ctx, APX_EINVAL, "switch_kind must be 0 or 1");
+  if (!(p->r_cut > 0.0) || p->r_cut > nl->r_list) return fail(ctx, APX_EINVAL, "r_cut must be in (0, r_list]");
+  if (p->r_hi > 0.0 && !(p->r_hi > p->r_lo)) return fail(ctx, APX_EINVAL, "r_hi must exceed r_lo");
+  *n_active = 0;
+  if (n == 0) return APX_OK;
+  Grid g = make_grid(atoms, nl->r_list);
+  PrecDev pd;
+  pd.n_nn = p->n_nn;
+  pd.m = p->n_nn + p->n_buffer;
+  pd.half = p->n_nn / 2;
+  pd.kind = p->switch_kind;
+  pd.csp_lo = p->csp_lo;
+  pd.width = p->csp_hi - p->csp_lo;
+  pd.rc2 = p->r_cut * p->r_cut;
+  k_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, g, atoms->frozen, nl->count, nl->idx,
+                                                     nl->max_nb, pd, w0_extra, csp, w0, w);
+  APX_LAUNCH_CHECK(ctx);
+  if (p->r_hi > 0.0) {
+    APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
+    APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * 4);
+    APX_HIP(ctx, hipMemsetAsync(ctx->itmp2.p, 0, sizeof(int), ctx->stream));
+    k_sources<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w0, atoms->frozen, ctx->itmp.as<int>(),
+                                                          ctx->itmp2.as<int>());
+    APX_LAUNCH_CHECK(ctx);
+    int nsrc = 0;
+    s = read_ints(ctx, ctx->itmp2.as<int>(), &nsrc, 1);
+    if (s != APX_OK) return s;
+    if (nsrc > 0) {
+      Grid gs = make_grid(atoms, p->r_hi / 3.0);
+      s = bin_atoms(ctx, atoms, gs);
+      if (s != APX_OK) return s;
+      SpreadDev sd;
+      sd.r_lo = p->r_lo;
+      sd.width = p->r_hi - p->r_lo;
+      sd.rh2 = p->r_hi * p->r_hi;
+      spread_stencil(gs, p->r_hi, sd);
+      const long long threads = (long long)nsrc * kWave;
+      k_spread<<<blocks_for(threads, 256), 256, 0, ctx->stream>>>(
+          atoms->pos, n, gs, sd, ctx->itmp.as<int>(), nsrc, w0, atoms->frozen, ctx->cell_start.as<int>(),
+          ctx->cell_atoms.as<int>(), reinterpret_cast<unsigned long long*>(w));
+      APX_LAUNCH_CHECK(ctx);
+    }
+  }
+  APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
+  APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
+  k_mask<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, mask, ctx->itmp.as<int>());
+  APX_LAUNCH_CHECK(ctx);
+  s = scan_exclusive(ctx, ctx->itmp.as<int>(), n, ctx->itmp2.as<int>());
+  if (s != APX_OK) return s;
+  k_compact<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->itmp.as<int>(), ctx->itmp2.as<int>(), active);
+  APX_LAUNCH_CHECK(ctx);
+  int na = 0;
+  s = read_ints(ctx, ctx->itmp2.as<int>() + n, &na, 1);
+  if (s != APX_OK) return s;
+  *n_active = na;
+  return APX_OK;
+}

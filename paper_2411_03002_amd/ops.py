@@ -1,0 +1,324 @@
+"""Tensor-level wrappers of the C ABI (argument marshalling only).
+
+Every function here hands device pointers of torch tensors to libapx.so and returns
+the tensors the library filled.  Parameter objects are duck-typed: any object with the
+attribute names of the corresponding apx.h structure works.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An apx_ctx bound to a device; every call enqueues on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.lib = B.load()
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(self.torch_device).cuda_stream
+        self._check(self.lib.apx_ctx_create(device, C.c_void_p(stream), C.byref(h)), h)
+        self.h = h
+
+    def _check(self, code, h=None):
+        if code != B.APX_OK:
+            msg = self.lib.apx_last_error(h if h is not None else self.h)
+            raise B.ApxError(code, (msg or b"").decode())
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.torch_device).cuda_stream
+        self.lib.apx_ctx_set_stream(self.h, C.c_void_p(s))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.apx_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class DeviceAtoms:
+    pos: torch.Tensor  # [3, n] float64 cuda
+    lo: tuple
+    hi: tuple
+    periodic: tuple
+    frozen: torch.Tensor | None = None  # [n] uint8 cuda
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[1])
+
+    def struct(self) -> B.Atoms:
+        a = B.Atoms()
+        a.n = self.n
+        a.pos = self.pos.data_ptr() if self.n else None
+        for d in range(3):
+            a.lo[d] = float(self.lo[d])
+            a.hi[d] = float(self.hi[d])
+            a.periodic[d] = int(bool(self.periodic[d]))
+        a.frozen = None if self.frozen is None else self.frozen.data_ptr()
+        return a
+
+
+def device_atoms(system, device="cuda") -> DeviceAtoms:
+    """Copies a host configuration (``pos`` [3, n], ``lo``, ``hi``, ``periodic``, ``frozen``)."""
+    pos = torch.as_tensor(np.ascontiguousarray(system.pos), dtype=torch.float64).to(device).contiguous()
+    frozen = None
+    if getattr(system, "frozen", None) is not None:
+        frozen = torch.as_tensor(np.ascontiguousarray(system.frozen, dtype=np.uint8)).to(device)
+    return DeviceAtoms(pos, tuple(map(float, system.lo)), tuple(map(float, system.hi)),
+                       tuple(int(p) for p in system.periodic), frozen)
+
+
+@dataclasses.dataclass
+class NeighborList:
+    count: torch.Tensor  # [n] int32
+    idx: torch.Tensor  # [max_nb, n] int32
+    max_nb: int
+    r_list: float
+    needed: int = 0
+
+    def struct(self) -> B.NList:
+        s = B.NList()
+        s.n = int(self.count.shape[0])
+        s.max_nb = int(self.max_nb)
+        s.count = self.count.data_ptr() if s.n else None
+        s.idx = self.idx.data_ptr() if s.n else None
+        s.r_list = float(self.r_list)
+        return s
+
+
+def build_neighbors(ctx: Context, atoms: DeviceAtoms, r_list: float, max_nb: int = 80,
+                    grow: bool = True) -> NeighborList:
+    """apx_build_neighbors; with ``grow`` a too-small capacity is enlarged once."""
+    ctx.bind_stream()
+    n = atoms.n
+    for attempt in range(2):
+        count = torch.empty(n, dtype=torch.int32, device=atoms.pos.device)
+        idx = torch.empty((max_nb, n), dtype=torch.int32, device=atoms.pos.device)
+        nl = NeighborList(count, idx, max_nb, r_list)
+        st = nl.struct()
+        a = atoms.struct()
+        needed = C.c_int32(0)
+        code = ctx.lib.apx_build_neighbors(ctx.h, C.byref(a), float(r_list), C.byref(st), C.byref(needed))
+        nl.needed = int(needed.value)
+        if code == B.APX_ECAPACITY and grow and attempt == 0 and nl.needed <= 128:
+            max_nb = nl.needed
+            continue
+        ctx._check(code)
+        return nl
+    raise RuntimeError("unreachable")
+
+
+def prec_struct(p) -> B.PrecParams:
+    s = B.PrecParams()
+    s.n_nn = int(getattr(p, "n_nn", 12))
+    s.n_buffer = int(getattr(p, "n_buffer", 0))
+    s.switch_kind = int(p.switch_kind)
+    s.csp_lo = float(p.csp_lo)
+    s.csp_hi = float(p.csp_hi)
+    s.r_cut = float(getattr(p, "r_cut", 5.0))
+    s.r_lo = float(getattr(p, "r_lo", 0.0))
+    s.r_hi = float(getattr(p, "r_hi", 0.0))
+    return s
+
+
+def eam_struct(p) -> B.EamParams:
+    s = B.EamParams()
+    s.A, s.alpha, s.beta, s.r0 = float(p.A), float(p.alpha), float(p.beta), float(p.r0)
+    s.r_cut = float(getattr(p, "rc", getattr(p, "r_cut", 5.0)))
+    s.h = float(p.h)
+    return s
+
+
+def compute_precision(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w0_extra=None) -> dict:
+    ctx.bind_stream()
+    n = atoms.n
+    dev = atoms.pos.device
+    out = dict(csp=torch.empty(n, dtype=torch.float64, device=dev),
+               w0=torch.empty(n, dtype=torch.float64, device=dev),
+               w=torch.empty(n, dtype=torch.float64, device=dev),
+               mask=torch.empty(n, dtype=torch.uint8, device=dev),
+               active=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+    na = C.c_int64(0)
+    a, s, pp = atoms.struct(), nl.struct(), prec_struct(params)
+    ctx._check(ctx.lib.apx_compute_precision(ctx.h, C.byref(a), C.byref(s), C.byref(pp), _p(w0_extra),
+                                             _p(out["csp"]), _p(out["w0"]), _p(out["w"]), _p(out["mask"]),
+                                             _p(out["active"]), C.byref(na)))
+    out["n_active"] = int(na.value)
+    out["active"] = out["active"][: out["n_active"]]
+    return out
+
+
+def eam_forces(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w=None) -> dict:
+    ctx.bind_stream()
+    n = atoms.n
+    dev = atoms.pos.device
+    out = dict(e_site=torch.empty(n, dtype=torch.float64, device=dev),
+               rho=torch.empty(n, dtype=torch.float64, device=dev),
+               f=torch.empty((3, n), dtype=torch.float64, device=dev))
+    a, s, ep = atoms.struct(), nl.struct(), eam_struct(params)
+    ctx._check(ctx.lib.apx_eam_forces(ctx.h, C.byref(a), C.byref(s), C.byref(ep), _p(w), _p(out["e_site"]),
+                                      _p(out["rho"]), _p(out["f"])))
+    return out
+
+
+def num_basis(n_max: int, l_max: int) -> int:
+    return int(B.load().apx_ace_num_basis(n_max, l_max))
+
+
+class AceModel:
+    """Device copy of an ACE parameter set (n_max, l_max, W, c1, c2, rc, h, s_a, eps, anchor)."""
+
+    def __init__(self, ctx: Context, prm):
+        self.ctx = ctx
+        self.n_max, self.l_max = int(prm.n_max), int(prm.l_max)
+        self.n_basis = num_basis(self.n_max, self.l_max)
+        W = np.ascontiguousarray(prm.W, dtype=np.float64)
+        c1 = np.ascontiguousarray(prm.c1, dtype=np.float64)
+        c2 = np.ascontiguousarray(prm.c2, dtype=np.float64)
+        if W.shape != (self.l_max + 1, self.n_max, self.n_max) or c1.size != self.n_basis or c2.size != self.n_basis:
+            raise ValueError("ACE parameter shapes do not match the basis")
+        d = B.AceDesc()
+        d.n_max, d.l_max = self.n_max, self.l_max
+        d.r_cut = float(getattr(prm, "rc", 5.0))
+        d.h = float(getattr(prm, "h", 0.5))
+        d.s_a = float(getattr(prm, "s_a", 1.0))
+        d.eps = float(getattr(prm, "eps", 0.1))
+        d.W, d.c1, d.c2 = W.ctypes.data, c1.ctypes.data, c2.ctypes.data
+        anchor = getattr(prm, "anchor", None)
+        d.anchored = 1 if anchor is not None else 0
+        if anchor is not None:
+            d.anchor = eam_struct(anchor)
+        self._keep = (W, c1, c2)
+        h = C.c_void_p()
+        ctx._check(ctx.lib.apx_ace_model_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.apx_ace_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ace_energy_forces(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, model: AceModel,
+                      active: torch.Tensor, w=None, precision: str = "fp64", want_dc: bool = False) -> dict:
+    ctx.bind_stream()
+    n = atoms.n
+    dev = atoms.pos.device
+    out = dict(e_site=torch.empty(n, dtype=torch.float64, device=dev),
+               f=torch.empty((3, n), dtype=torch.float64, device=dev))
+    dc1 = dc2 = None
+    if want_dc:
+        dc1 = torch.empty(model.n_basis, dtype=torch.float64, device=dev)
+        dc2 = torch.empty(model.n_basis, dtype=torch.float64, device=dev)
+    active = active.to(torch.int32).contiguous()
+    prec = B.APX_FP32 if precision == "fp32" else B.APX_FP64
+    a, s = atoms.struct(), nl.struct()
+    ctx._check(ctx.lib.apx_ace_energy_forces(ctx.h, C.byref(a), C.byref(s), model.h, _p(w), _p(active),
+                                             int(active.numel()), prec, _p(out["e_site"]), _p(out["f"]),
+                                             _p(dc1), _p(dc2)))
+    if want_dc:
+        out["dE_dc1"], out["dE_dc2"] = dc1, dc2
+    return out
+
+
+def blend(ctx: Context, w, e_eam, e_ace, f_eam, f_ace) -> dict:
+    ctx.bind_stream()
+    n = int(e_eam.numel())
+    dev = e_eam.device
+    out = dict(e_site=torch.empty(n, dtype=torch.float64, device=dev),
+               f=torch.empty((3, n), dtype=torch.float64, device=dev),
+               e_pot=torch.empty(1, dtype=torch.float64, device=dev))
+    ctx._check(ctx.lib.apx_blend(ctx.h, n, _p(w), _p(e_eam), _p(e_ace), _p(f_eam), _p(f_ace),
+                                 _p(out["e_site"]), _p(out["f"]), _p(out["e_pot"])))
+    return out
+
+
+class MD:
+    """Device-resident velocity-Verlet integrator (apx_md_*)."""
+
+    def __init__(self, ctx: Context, atoms: DeviceAtoms, eam, ace: AceModel | None, prec, *, dt=1e-3,
+                 mass=63.546, skin=0.5, max_nb=80, precision_every=10, ace_precision="fp32",
+                 mode="adaptive", indenter=None):
+        self.ctx = ctx
+        self.atoms = atoms
+        p = B.MdParams()
+        p.dt, p.mass, p.skin, p.max_nb = float(dt), float(mass), float(skin), int(max_nb)
+        p.precision_every = int(precision_every)
+        p.ace_precision = B.APX_FP32 if ace_precision == "fp32" else B.APX_FP64
+        p.mode = {"adaptive": B.MODE_ADAPTIVE, "full_ace": B.MODE_FULL_ACE, "eam": B.MODE_EAM}[mode]
+        if indenter is not None:
+            p.indenter = 1
+            p.ind_radius = float(indenter["radius"])
+            p.ind_k = float(indenter["k"])
+            for d in range(3):
+                p.ind_center[d] = float(indenter["center"][d])
+                p.ind_velocity[d] = float(indenter["velocity"][d])
+        self._params = p
+        self._eam = eam_struct(eam)
+        self._prec = prec_struct(prec) if prec is not None else None
+        a = atoms.struct()
+        h = C.c_void_p()
+        ctx.bind_stream()
+        ctx._check(ctx.lib.apx_md_create(ctx.h, C.byref(a), C.byref(p), C.byref(self._eam),
+                                         ace.h if ace is not None else None,
+                                         C.byref(self._prec) if self._prec is not None else None, C.byref(h)))
+        self.h = h
+        self.ace = ace
+
+    def init(self, pos: torch.Tensor):
+        self.ctx.bind_stream()
+        n = pos.shape[1]
+        f = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        w = torch.empty(n, dtype=torch.float64, device=pos.device)
+        self.ctx._check(self.ctx.lib.apx_md_init(self.h, _p(pos), _p(f), _p(w)))
+        return f, w
+
+    def step(self, pos, vel, f, w, n_steps: int) -> dict:
+        self.ctx.bind_stream()
+        st = B.MdStats()
+        self.ctx._check(self.ctx.lib.apx_verlet_step(self.h, _p(pos), _p(vel), _p(f), _p(w), int(n_steps),
+                                                     C.byref(st)))
+        return {k: getattr(st, k) for k, _ in B.MdStats._fields_}
+
+    def timings(self) -> list:
+        arr = (C.c_double * 5)()
+        self.ctx._check(self.ctx.lib.apx_md_timings(self.h, arr))
+        return list(arr)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.apx_md_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,284 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle on seeded inputs.
+
+Bars: neighbour rows, CSP-derived masks and active lists bit-exact; CSP, w0 and w
+bit-exact (same operation order, no fused operations on either side); float64 energies
+and forces within 1e-10 (eV, eV/A); float32 ACE forces within the 10 meV/A budget.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from synth import configs
+from oracle import ace as oace
+from oracle import geometry, hybrid, precision, verlet
+
+pytestmark = pytest.mark.gpu
+
+FTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ops_ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_03002_amd import ops
+    return ops, ops.Context(0)
+
+
+def _case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def _systems():
+    out = {
+        "cfg0": configs.cfg0(),
+        "cfg0_static": configs.cfg0_static(),
+        "slab100_4x4x6": configs.slab100(4, 4, 6, seed=5, temperature=300.0, sigma=0.05),
+        "void_bulk8": configs.bulk(8, seed=6, temperature=300.0, void_radius=6.0),
+    }
+    return out
+
+
+SYSTEMS = _systems()
+
+
+def _rows(nl):
+    cnt = nl.count.cpu().numpy()
+    idx = nl.idx.cpu().numpy()
+    return cnt, idx
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_neighbor_rows_bit_exact(ops_ctx, name):
+    ops, ctx = ops_ctx
+    _case(f"neighbors {name}")
+    s = SYSTEMS[name]
+    nl = ops.build_neighbors(ctx, ops.device_atoms(s), 5.5)
+    off, idx = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    cnt, rows = _rows(nl)
+    assert np.array_equal(cnt, np.diff(off))
+    for i in range(s.n):
+        assert np.array_equal(rows[: cnt[i], i], idx[off[i]:off[i + 1]]), i
+    assert nl.needed == int(np.diff(off).max())
+
+
+def test_neighbor_rows_16k_with_vacancies(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("neighbors cfg3 vac (16,376 atoms)")
+    s = configs.cfg3("vac")
+    nl = ops.build_neighbors(ctx, ops.device_atoms(s), 5.5)
+    off, idx = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    cnt, rows = _rows(nl)
+    assert np.array_equal(cnt, np.diff(off))
+    flat = np.concatenate([rows[: cnt[i], i] for i in range(s.n)])
+    assert np.array_equal(flat, idx)
+
+
+def test_neighbor_capacity_error(ops_ctx):
+    ops, ctx = ops_ctx
+    from paper_2411_03002_amd import binding
+    _case("neighbors capacity")
+    s = SYSTEMS["cfg0"]
+    with pytest.raises(binding.ApxError) as ei:
+        ops.build_neighbors(ctx, ops.device_atoms(s), 5.5, max_nb=20, grow=False)
+    assert ei.value.code == binding.APX_ECAPACITY
+    nl = ops.build_neighbors(ctx, ops.device_atoms(s), 5.5, max_nb=20, grow=True)
+    assert nl.max_nb >= 54
+
+
+def test_empty_and_tiny_inputs(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("tiny inputs")
+    pos = np.array([[0.0, 2.5], [0.0, 0.0], [0.0, 0.0]])
+    s = synth.System(pos, np.full(3, -20.0), np.full(3, 20.0), (0, 0, 0))
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5)
+    assert nl.count.cpu().tolist() == [1, 1]
+    pr = ops.compute_precision(ctx, atoms, nl, synth.precision_hyb1())
+    assert np.all(np.isinf(pr["csp"].cpu().numpy()))
+    assert pr["n_active"] == 2
+    e = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), pr["w"])
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    ref = hybrid.evaluate(s, synth.eam_cu_like(), None, pr["w"].cpu().numpy(), csr)
+    assert np.allclose(e["f"].cpu().numpy(), ref["f_eam"], atol=FTOL, rtol=0)
+
+
+PREC_CASES = {
+    "cfg0_linear": ("cfg0", synth.precision_cfg0()),
+    "cfg0_static_spread": ("cfg0_static", synth.precision_static()),
+    "slab_hyb1_spread": ("slab100_4x4x6", synth.PrecisionParams(2.5, 3.0, 1, 4.0, 8.0)),
+    "void_hyb1_spread": ("void_bulk8", synth.PrecisionParams(2.5, 3.0, 1, 4.0, 8.0)),
+}
+
+
+@pytest.mark.parametrize("case", list(PREC_CASES))
+def test_precision_bit_exact(ops_ctx, case):
+    ops, ctx = ops_ctx
+    _case(f"precision {case}")
+    name, prm = PREC_CASES[case]
+    s = SYSTEMS[name]
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5)
+    pr = ops.compute_precision(ctx, atoms, nl, prm)
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    ref = precision.compute_precision(s, prm, csr)
+    for k in ("csp", "w0", "w"):
+        got = pr[k].cpu().numpy()
+        assert np.array_equal(got, ref[k]), (k, np.abs(got - ref[k]).max())
+    assert np.array_equal(pr["mask"].cpu().numpy(), ref["mask"])
+    assert np.array_equal(pr["active"].cpu().numpy(), ref["active"])
+    assert 0 < pr["n_active"] <= s.n
+
+
+@pytest.mark.parametrize("name", ["cfg0", "slab100_4x4x6"])
+def test_eam_parity(ops_ctx, name):
+    ops, ctx = ops_ctx
+    _case(f"eam {name}")
+    s = SYSTEMS[name]
+    w = np.random.default_rng(3).uniform(size=s.n)
+    w[::3] = 0.0
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5)
+    e = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), torch.as_tensor(w, device="cuda"))
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    ref = hybrid.evaluate(s, synth.eam_cu_like(), None, w, csr)
+    assert np.allclose(e["e_site"].cpu().numpy(), ref["e_eam"], atol=FTOL, rtol=0)
+    assert np.allclose(e["rho"].cpu().numpy(), ref["rho"], atol=FTOL, rtol=0)
+    assert np.allclose(e["f"].cpu().numpy(), ref["f_eam"], atol=FTOL, rtol=0)
+
+
+ACE_CASES = {
+    "cfg0_8_3_random": ("cfg0", 8, 3, False),
+    "slab_10_4_anchored": ("slab100_4x4x6", 10, 4, True),
+}
+
+
+def _ace_setup(ops, ctx, case):
+    name, nm, lm, anch = ACE_CASES[case]
+    s = SYSTEMS[name]
+    prm = synth.ace_random(nm, lm, oace.num_basis(nm, lm), seed=21, anchored=anch)
+    rng = np.random.default_rng(8)
+    w = np.where(rng.uniform(size=s.n) < 0.5, 0.0, rng.uniform(0.05, 1.0, size=s.n))
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5)
+    model = ops.AceModel(ctx, prm)
+    active = torch.as_tensor(np.nonzero(w > 0)[0].astype(np.int32), device="cuda")
+    return s, prm, w, atoms, nl, model, active
+
+
+@pytest.mark.parametrize("case", list(ACE_CASES))
+def test_ace_fp64_parity(ops_ctx, case):
+    ops, ctx = ops_ctx
+    _case(f"ace fp64 {case}")
+    s, prm, w, atoms, nl, model, active = _ace_setup(ops, ctx, case)
+    out = ops.ace_energy_forces(ctx, atoms, nl, model, active, torch.as_tensor(w, device="cuda"), "fp64")
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    ref = hybrid.evaluate(s, synth.eam_cu_like(), prm, w, csr)
+    e = out["e_site"].cpu().numpy()
+    assert np.allclose(e, np.where(w > 0, ref["e_ace"], 0.0), atol=FTOL, rtol=0), np.abs(e - ref["e_ace"]).max()
+    f = out["f"].cpu().numpy()
+    assert np.allclose(f, ref["f_ace"], atol=FTOL, rtol=0), np.abs(f - ref["f_ace"]).max()
+
+
+@pytest.mark.parametrize("case", list(ACE_CASES))
+def test_ace_fp32_error_budget(ops_ctx, case):
+    ops, ctx = ops_ctx
+    _case(f"ace fp32 {case}")
+    s, prm, w, atoms, nl, model, active = _ace_setup(ops, ctx, case)
+    wt = torch.as_tensor(w, device="cuda")
+    o32 = ops.ace_energy_forces(ctx, atoms, nl, model, active, wt, "fp32")
+    o64 = ops.ace_energy_forces(ctx, atoms, nl, model, active, wt, "fp64")
+    df = (o32["f"] - o64["f"]).abs().max().item()
+    de = (o32["e_site"] - o64["e_site"]).abs().max().item()
+    print(f"fp32 vs fp64: max|dF| = {df * 1e3:.5f} meV/A, max|dE_i| = {de * 1e3:.5f} meV")
+    assert df < 1e-2
+    assert de < 1e-3
+
+
+def test_coefficient_gradients(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("ace dE/dc cfg0")
+    s, prm, w, atoms, nl, model, active = _ace_setup(ops, ctx, "cfg0_8_3_random")
+    out = ops.ace_energy_forces(ctx, atoms, nl, model, active, torch.as_tensor(w, device="cuda"), "fp64",
+                                want_dc=True)
+    i, j = geometry.pairs_within(s.pos, s.lo, s.hi, s.periodic, prm.rc)
+    c1 = torch.tensor(prm.c1, requires_grad=True)
+    c2 = torch.tensor(prm.c2, requires_grad=True)
+    sites = np.nonzero(w > 0)[0]
+    e = oace.site_energies(torch.as_tensor(s.pos), s.box, s.periodic, i, j, prm, s.n, sites, c1, c2)
+    g1, g2 = torch.autograd.grad((torch.as_tensor(w) * e).sum(), (c1, c2))
+    assert np.allclose(out["dE_dc1"].cpu().numpy(), g1.numpy(), atol=1e-10, rtol=0)
+    assert np.allclose(out["dE_dc2"].cpu().numpy(), g2.numpy(), atol=1e-10, rtol=0)
+
+
+def test_blend_parity(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("blend cfg0")
+    s, prm, w, atoms, nl, model, active = _ace_setup(ops, ctx, "cfg0_8_3_random")
+    wt = torch.as_tensor(w, device="cuda")
+    e = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), wt)
+    a = ops.ace_energy_forces(ctx, atoms, nl, model, active, wt, "fp64")
+    b = ops.blend(ctx, wt, e["e_site"], a["e_site"], e["f"], a["f"])
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    ref = hybrid.evaluate(s, synth.eam_cu_like(), prm, w, csr)
+    assert np.allclose(b["e_site"].cpu().numpy(), ref["e_site"], atol=FTOL, rtol=0)
+    assert np.allclose(b["f"].cpu().numpy(), ref["f"], atol=FTOL, rtol=0)
+    assert abs(b["e_pot"].item() - ref["e_pot"]) < 1e-8
+
+
+def test_weight_limits(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("weight limits cfg0")
+    s = SYSTEMS["cfg0"]
+    prm = synth.ace_random(8, 3, oace.num_basis(8, 3), seed=21)
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5)
+    model = ops.AceModel(ctx, prm)
+    zeros = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    ones = torch.ones(s.n, dtype=torch.float64, device="cuda")
+    e0 = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), zeros)
+    enul = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), None)
+    assert torch.equal(e0["f"], enul["f"])
+    e1 = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), ones)
+    assert e1["f"].abs().max().item() == 0.0
+    all_idx = torch.arange(s.n, dtype=torch.int32, device="cuda")
+    a1 = ops.ace_energy_forces(ctx, atoms, nl, model, all_idx, ones, "fp64")
+    anul = ops.ace_energy_forces(ctx, atoms, nl, model, all_idx, None, "fp64")
+    assert torch.allclose(a1["f"], anul["f"], atol=1e-14, rtol=0)
+    b = ops.blend(ctx, ones, e1["e_site"], a1["e_site"], e1["f"], a1["f"])
+    assert torch.equal(b["e_site"], a1["e_site"])
+    none_idx = torch.zeros(0, dtype=torch.int32, device="cuda")
+    a0 = ops.ace_energy_forces(ctx, atoms, nl, model, none_idx, zeros, "fp64")
+    assert a0["f"].abs().max().item() == 0.0 and a0["e_site"].abs().max().item() == 0.0
+    f_sum = (e0["f"].sum(dim=1)).abs().max().item()
+    assert f_sum < 1e-10 and a1["f"].sum(dim=1).abs().max().item() < 1e-10
+
+
+def test_verlet_matches_oracle(ops_ctx):
+    ops, ctx = ops_ctx
+    _case("verlet cfg0 fixed weights, 8 steps")
+    s = SYSTEMS["cfg0"].copy()
+    s.vel = synth.maxwell_velocities(s.n, 300.0, np.random.default_rng(4))
+    prm = synth.ace_random(8, 3, oace.num_basis(8, 3), seed=21, anchored=True)
+    eam_p = synth.eam_cu_like()
+    pr_p = synth.precision_cfg0()
+    atoms = ops.device_atoms(s)
+    model = ops.AceModel(ctx, prm)
+    md = ops.MD(ctx, atoms, eam_p, model, pr_p, dt=1e-3, precision_every=4, ace_precision="fp64",
+                mode="adaptive")
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(s.vel, device="cuda").contiguous()
+    f, w = md.init(pos)
+    st = md.step(pos, vel, f, w, 8)
+    ref = verlet.run(s, eam_p, prm, pr_p, dt=1e-3, n_steps=8, precision_every=4)
+    d = pos.cpu().numpy() - ref["x"]
+    d -= s.box[:, None] * np.round(d / s.box[:, None])
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(vel.cpu().numpy() - ref["v"]).max() < 1e-7
+    assert np.array_equal(w.cpu().numpy() > 0, ref["w"] > 0)
+    assert abs(st["e_pot"] - ref["e_pot"][-1]) < 1e-7
+    assert st["precision_updates"] == 2
