@@ -1,0 +1,244 @@
+"""Benchmark: adaptive vs full-ACE atom-steps/s on one MI355X, plus force error vs FP64.
+
+Workload: the nanoindentation-like block of 100x100x100 FCC cells (4,000,000 Cu-like
+atoms, x/y periodic, free z surfaces, bottom three (002) planes frozen, spherical
+indenter R = 40 A, K = 10 eV/A^3, 0.2 A/ps, 300 K Maxwell velocities), anchored
+synthetic ACE (n_max 10, l_max 4) evaluated in float32 where the precise weight is
+non-zero, float64 EAM everywhere, Hyb1 detection (CSP 2.5/3.0 A^2, spreading 4/12 A)
+recomputed every 10 steps, float64 velocity Verlet at dt = 1 fs.
+
+One step = one velocity-Verlet step through the library (neighbour rebuild when needed,
+weights every 10 steps, EAM, ACE, blend, indenter, integration).  W warm-up steps, then
+exactly K timed steps between synchronisations; the same is repeated with the full-ACE
+integrator (ACE for every atom, no EAM, no detection) on the same initial state.
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cells", type=int, default=100)
+    ap.add_argument("--full-steps", type=int, default=None, help="timed full-ACE steps (default: --steps)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-full", action="store_true", help="skip the full-ACE comparison")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the adaptive timed region (for external profilers)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_models(stats, n, n_act, nb_avg, nb_act_avg):
+    """Algorithmic work per launch of each kernel: (bound, amount, unit).
+
+    HBM kernels count the bytes a kernel must move (each array element once, the
+    neighbour row once, gathered neighbour data assumed cached); ALU kernels count the
+    floating-point operations of the algorithm as implemented (fma = 2 flops).
+    """
+    Tc, Tw, Nt = stats["coupling_terms"], stats["triple_width"], stats["triples"]
+    # energy: coupling 3/term, triples 2 per (2L+1) and 4 per triple; adjoint: coupling
+    # recompute 3/term and back-propagation 5/term, triples 4 per (2L+1) and 2 per triple
+    f_products = 11.0 * Tc + 6.0 * Tw + 6.0 * Nt
+    K, LM = 10, 25
+    f_basis = nb_act_avg * (3 * K + 4 * LM + 2 * K * LM) + 2.0 * K * stats["n_atomic_base"]
+    f_force = 2.0 * K * stats["n_atomic_base"] + nb_act_avg * (4 * K * LM + 12 * LM + 6 * K)
+    row = 4.0 + 4.0 * nb_avg
+    return {
+        "ace.products": ("mfma_free_alu_fp32", n_act * f_products, "flop"),
+        "ace.basis": ("alu_fp32", n_act * f_basis, "flop"),
+        "ace.force": ("alu_fp32", n_act * f_force, "flop"),
+        "eam.density": ("hbm", n * (row + 24 + 8 + 32), "byte"),
+        "eam.force": ("hbm", n * (row + 24 + 16 + 24), "byte"),
+        "nbr.build": ("hbm", n * (24 + row), "byte"),
+        "prec.csp": ("hbm", n * (row + 24 + 24), "byte"),
+        "md.kick_drift": ("hbm", n * (24 * 4 + 24), "byte"),
+        "md.kick": ("hbm", n * 72, "byte"),
+        "blend": ("hbm", n * (8 * 3 + 48 + 8 + 24), "byte"),
+    }
+
+
+def roofline_for(name, model, launches, total_ms):
+    bound, amount, unit = model
+    avg_s = total_ms / 1e3 / max(launches, 1)
+    if unit == "byte":
+        achieved = amount / avg_s / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_ms": avg_s * 1e3,
+                "work_per_launch": amount}
+    achieved = amount / avg_s / 1e12
+    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "avg_ms": avg_s * 1e3,
+            "work_per_launch": amount}
+
+
+def cpu_baseline(sample_cells=(8, 8, 100), budget_s=30.0):
+    """The oracle timed on a column of the same workload: full height, small x/y extent.
+
+    The column keeps the layer structure (free top surface, frozen bottom planes), so
+    its detected fraction matches the full block.  One step of the oracle = precision
+    (CSP, switch, spreading) + hybrid energy and forces (EAM everywhere, ACE on w > 0).
+    """
+    import torch
+    import synth
+    from synth import configs
+    from oracle import ace as oace
+    from oracle import geometry, hybrid, precision
+    nx, ny, nz = sample_cells
+    s = configs.slab100(nx, ny, nz, seed=configs.SEED0 + 2, temperature=300.0)
+    prm = synth.ace_random(10, 4, oace.num_basis(10, 4), seed=4242, anchored=True)
+    t0 = time.perf_counter()
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    pr = precision.compute_precision(s, synth.precision_hyb1(), csr)
+    ev = hybrid.evaluate(s, synth.eam_cu_like(), prm, pr["w"], csr)
+    dt = time.perf_counter() - t0
+    return {"value": s.n / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one adaptive force evaluation (neighbours, CSP, spreading, EAM, ACE n_max 10 l_max 4 "
+                      f"on {int(pr['active'].size)} detected atoms) of a {nx}x{ny}x{nz}-cell column "
+                      f"({s.n} atoms) of the indentation block, {dt:.1f} s",
+            "active_fraction": float(pr["active"].size) / s.n, "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import synth
+    from synth import configs
+    from paper_2411_03002_amd import ops
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    K, W = args.steps, args.warmup
+    KF = args.full_steps if args.full_steps is not None else K
+    cells = args.cells
+    log(f"building {cells}^3-cell indentation block")
+    s = configs.cfg2(cells=cells)
+    ind = s.meta["indenter"]
+    n = s.n
+    nb = ops.num_basis(10, 4)
+    prm = synth.ace_random(10, 4, nb, seed=4242, anchored=True)
+    eam_p = synth.eam_cu_like()
+    prec = synth.precision_hyb1()
+    ctx = ops.Context(0)
+    atoms = ops.device_atoms(s)
+    model = ops.AceModel(ctx, prm)
+    stats = model.stats()
+    vel0 = torch.as_tensor(s.vel, dtype=torch.float64, device="cuda").contiguous()
+
+    def run(mode, steps, warm, profile):
+        md = ops.MD(ctx, atoms, eam_p, model, prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
+                    ace_precision="fp32", mode=mode, indenter=ind)
+        pos = atoms.pos.clone()
+        vel = vel0.clone()
+        f, w = md.init(pos)
+        if warm:
+            md.step(pos, vel, f, w, warm)
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(True)
+        t0 = time.perf_counter()
+        st = md.step(pos, vel, f, w, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read() if profile else {}
+        ctx.profile(False)
+        tim = md.timings()
+        md.close()
+        return dt, st, prof, tim
+
+    log(f"adaptive: {W} warm-up + {K} timed steps on {n} atoms")
+    dt_a, st_a, prof_a, tim_a = run("adaptive", K, W, True)
+    adaptive = n * K / dt_a
+    log(f"adaptive {dt_a / K * 1e3:.3f} ms/step, {adaptive:.4g} atom-steps/s, active {st_a['n_active']}")
+    result = {
+        "metric": "adaptive vs full-ACE atom-steps/s on 1 GPU; force err (meV/A) vs FP64",
+        "value": adaptive, "unit": "atom-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": dt_a / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 ACE / f64 EAM, neighbours, integration", "data": "synthetic",
+        "config": {"workload": f"nanoindentation block {cells}^3 FCC cells, {n} atoms, x/y periodic, free z, "
+                               f"3 frozen (002) planes, indenter R 40 A K 10 eV/A^3 0.2 A/ps, 300 K, "
+                               f"anchored ACE n_max 10 l_max 4 (float32), Hyb1 detection every 10 steps",
+                   "atoms": n, "dt_fs": 1.0, "precision_every": 10},
+        "active_atoms": int(st_a["n_active"]), "active_fraction": st_a["n_active"] / n,
+        "rebuilds": int(st_a["rebuilds"]),
+        "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
+                                      [t / K for t in tim_a])),
+    }
+    if args.profile_only:
+        print(json.dumps(result), flush=True)
+        return
+    # live per-kernel roofline of the adaptive timed region
+    nb_avg = 60.0
+    models = kernel_models(stats, n, st_a["n_active"], nb_avg, 42.0)
+    kern = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_a.items()}
+    dom = max(prof_a.items(), key=lambda kv: kv[1][1])[0]
+    result["kernels"] = kern
+    result["dominant_kernel"] = dom
+    roofs = {k: roofline_for(k, models[k], *prof_a[k]) for k in prof_a if k in models}
+    result["roofline"] = roofs.get(dom)
+    result["roofline_all"] = roofs
+
+    # force error of float32 ACE against float64 on the detected atoms at the start
+    log("float32 vs float64 ACE forces on the detected atoms")
+    nl = ops.build_neighbors(ctx, atoms, 5.5, max_nb=80)
+    pr = ops.compute_precision(ctx, atoms, nl, prec)
+    a64 = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp64")
+    a32 = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp32")
+    d = (a32["f"] - a64["f"]).abs()
+    wmask = pr["w"] > 0
+    dd = d[:, wmask]
+    result["force_err_fp32_vs_fp64_meV_per_A"] = {
+        "max": float(dd.max().item() * 1e3), "rms": float(dd.pow(2).mean().sqrt().item() * 1e3),
+        "atoms": int(wmask.sum().item())}
+    del nl, a64, a32, d, dd
+    torch.cuda.empty_cache()
+
+    if not args.no_full:
+        log(f"full ACE: 1 warm-up + {KF} timed steps")
+        dt_f, st_f, prof_f, tim_f = run("full_ace", KF, 1, True)
+        full = n * KF / dt_f
+        result["full_ace_atom_steps_per_s"] = full
+        result["full_ace_ms_per_step"] = dt_f / KF * 1e3
+        result["adaptive_over_full_ace"] = adaptive / full
+        mf = kernel_models(stats, n, n, nb_avg, 42.0)
+        if "ace.products" in prof_f:
+            result["roofline_full_ace_products"] = roofline_for("ace.products", mf["ace.products"],
+                                                                *prof_f["ace.products"])
+        result["kernels_full_ace"] = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
+                                      for k, v in prof_f.items()}
+        log(f"full ACE {dt_f / KF * 1e3:.2f} ms/step, {full:.4g} atom-steps/s, ratio {adaptive / full:.2f}")
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        result["cpu_baseline"] = cpu_baseline()
+    result["context"] = ("paper: 11.3x total core-h saving of the hybrid over full ACE for a 4M-atom Cu "
+                         "nanoindentation on JURECA-DC CPU cores (different core counts per run); no GPU figures")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,6 +57,15 @@ const char* apx_last_error(const apx_ctx* ctx);
 apx_status apx_ctx_synchronize(apx_ctx* ctx); /* (sync) */
 const char* apx_version(void);
 
+/* Per-kernel timing with HIP events recorded on the context stream around every
+ * kernel launch of the library (off by default).  Enabling resets the counters.
+ * apx_profile_count (sync) returns the number of kernel names seen; entry k gives the
+ * name (owned by the context), the number of launches and their summed duration. */
+apx_status apx_profile_enable(apx_ctx* ctx, int32_t on);
+int32_t apx_profile_count(apx_ctx* ctx);
+apx_status apx_profile_entry(apx_ctx* ctx, int32_t k, const char** name, int64_t* launches,
+                             double* total_ms);
+
 /* ------------------------------------------------------------------- atoms */
 typedef struct {
   int64_t n;             /* number of atoms */
@@ -155,6 +164,10 @@ typedef struct {
 } apx_ace_desc;
 
 int64_t apx_ace_num_basis(int32_t n_max, int32_t l_max);
+/* Work counts of a model per evaluated atom (host, no device work): out[0] label pairs,
+ * out[1] third-block terms (triples), out[2] coupling terms summed over pairs,
+ * out[3] sum over triples of (2L+1), out[4] product-basis size, out[5] atomic-base size. */
+apx_status apx_ace_model_stats(const apx_ace_model* m, int64_t* out6);
 /* Copies the descriptor's arrays to the device and builds the coupling tables. */
 apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* desc, apx_ace_model** out);
 void apx_ace_model_destroy(apx_ace_model* m);

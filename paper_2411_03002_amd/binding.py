@@ -74,6 +74,11 @@ PROTOTYPES = {
     "apx_last_error": (C.c_char_p, [_P]),
     "apx_ctx_synchronize": (C.c_int32, [_P]),
     "apx_version": (C.c_char_p, []),
+    "apx_profile_enable": (C.c_int32, [_P, C.c_int32]),
+    "apx_profile_count": (C.c_int32, [_P]),
+    "apx_profile_entry": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double)]),
+    "apx_ace_model_stats": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
     "apx_build_neighbors": (C.c_int32, [_P, C.POINTER(Atoms), C.c_double, C.POINTER(NList), C.POINTER(C.c_int32)]),
     "apx_compute_precision": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), C.POINTER(PrecParams), _P,
                                           _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),

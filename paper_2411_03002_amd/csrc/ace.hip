@@ -7,7 +7,8 @@
 //                    and real solid harmonics, A'[k][lm] = sum_j g_k S_lm, then the radial
 //                    mixing A[n][lm] = sum_k Wp[l][n][k] A'[k][lm] (Wp folds W, N_l, 1/s_a).
 //  2. k_ace_products lane = atom, 64 (fp32) or 32 (fp64) atoms per block held in LDS,
-//                    8 waves splitting the coupling list.  B3 is evaluated by recoupling:
+//                    16 (fp32) or 8 (fp64) waves dealt the coupling list round-robin;
+//                    the list is sorted by coupling type for instruction-cache locality.  B3 is evaluated by recoupling:
 //                    for a label pair (p1, p2) the coupled product
 //                    P_LM = sum G(l1 l2 L; m1 m2 M) A_p1m1 A_p2m2 is formed once and every
 //                    third block p3 >= p2 of degree L contributes B = sum_M P_LM A_p3M.
@@ -33,7 +34,8 @@ struct AnchorDev {
 template <class T>
 struct AceScratch {
   T* A;             // [n_act][na]
-  T* Ab;            // [n_act][na]
+  T* Ab;            // [n_act][na], or [tile][na][tile_size] when tile_size > 0
+  int tile_size;
   double* e_anch;   // [n_act]
   double* fp_anch;  // [n_act]
 };
@@ -274,13 +276,56 @@ __device__ __forceinline__ void pair_fwd(const T* __restrict__ As, const int* re
   for (int L = 0; L <= LMAX; ++L) {
     if ((C::kMask >> L) & 1) {
       const int q0 = rec[4 + L], q1 = rec[5 + L];
+      const int o3b = rec[10 + L];
+#pragma unroll 2
       for (int q = q0; q < q1; ++q) {
-        const int o3 = tb.t_off[q];
+        const int o3 = o3b + (q - q0) * P2;
+        const Coef2<T> c = tb.tc[q];
         T B = T(0);
 #pragma unroll
         for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[L * L + mm], As[(o3 + mm) * ST + t], B);
-        acc_add<T, COMP>(acc.s1, acc.e1, tb.t_c1[q], B);
-        acc_add<T, COMP>(acc.s2, acc.e2, tb.t_c2[q], B);
+        acc_add<T, COMP>(acc.s1, acc.e1, c.c1, B);
+        acc_add<T, COMP>(acc.s2, acc.e2, c.c2, B);
+      }
+    }
+  }
+}
+
+// Energy contribution of one label pair with the third-block loop unrolled over the
+// radial index (coefficient loads of a segment issued together).
+template <class T, int LMAX, int NMAX, int TILE, bool COMP, int L1, int L2>
+__device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
+                                           int n_max, Acc<T>& acc) {
+  using C = Couple<LMAX, L1, L2>;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  constexpr int ST = TILE + 1;
+  const int o1 = rec[0], o2 = rec[1];
+  T a[2 * L1 + 1], bb[2 * L2 + 1], P[P2];
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) a[m] = As[(o1 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) bb[m] = As[(o2 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < P2; ++m) P[m] = T(0);
+  C::template fwd<T>(a, bb, P);
+#pragma unroll
+  for (int L = 0; L <= LMAX; ++L) {
+    if ((C::kMask >> L) & 1) {
+      const int q0 = __builtin_amdgcn_readfirstlane(rec[4 + L]);
+      const int q1 = __builtin_amdgcn_readfirstlane(rec[5 + L]);
+      const int n30 = __builtin_amdgcn_readfirstlane((rec[10 + L] - L * L) / P2);
+      if (q0 < q1) {
+#pragma unroll
+        for (int n3 = 0; n3 < NMAX; ++n3) {
+          if (n3 >= n30 && n3 < n_max) {
+            const Coef2<T> c = tb.tc[q0 + n3 - n30];
+            T B = T(0);
+#pragma unroll
+            for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[L * L + mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
+            acc_add<T, COMP>(acc.s1, acc.e1, c.c1, B);
+            acc_add<T, COMP>(acc.s2, acc.e2, c.c2, B);
+          }
+        }
       }
     }
   }
@@ -309,10 +354,12 @@ __device__ __forceinline__ void pair_bwd(const T* __restrict__ As, T* __restrict
   for (int L = 0; L <= LMAX; ++L) {
     if ((C::kMask >> L) & 1) {
       const int q0 = rec[4 + L], q1 = rec[5 + L];
+      const int o3b = rec[10 + L];
+#pragma unroll 2
       for (int q = q0; q < q1; ++q) {
-        const int o3 = tb.t_off[q];
-        const T c1 = tb.t_c1[q], c2 = tb.t_c2[q];
-        const T d = fma(fp, c2, c1);
+        const int o3 = o3b + (q - q0) * P2;
+        const Coef2<T> c = tb.tc[q];
+        const T d = fma(fp, c.c2, c.c1);
         T B = T(0);
 #pragma unroll
         for (int mm = 0; mm < 2 * L + 1; ++mm) {
@@ -423,8 +470,8 @@ __device__ __forceinline__ T feps(T x, T eps, T& dfdx) {
   return x < T(0) ? -v : v;
 }
 
-template <class T, int LMAX, int TILE, bool COMP, bool DC>
-__global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __restrict__ Ag, T* __restrict__ Abg, int n_act,
+template <class T, int LMAX, int TILE, int NW, bool COMP, bool DC>
+__global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ Ag, T* __restrict__ Abg, int n_act,
                                                                  int na, AceTables<T> tb, int nb1, int nb2, T eps,
                                                                  const double* __restrict__ e_anch,
                                                                  const int* __restrict__ active,
@@ -435,10 +482,11 @@ __global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __rest
   extern __shared__ double smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Ab = As + (size_t)na * ST;
-  T* red = Ab + (size_t)na * ST;        // [kAceWaves][4][TILE]
-  T* fps = red + kAceWaves * 4 * TILE;  // [TILE]
+  T* red = Ab + (size_t)na * ST;  // [NW][4][TILE]
+  T* fps = red + NW * 4 * TILE;   // [TILE]
   const int tid = threadIdx.x;
-  const int nthr = kAceWaves * 64;
+  const int nthr = NW * 64;
+  const int npairs = tb.npairs;
   const int q0 = blockIdx.x * TILE;
   for (int e = tid; e < TILE * na; e += nthr) {
     const int t = e / na, a = e - t * na;
@@ -451,12 +499,13 @@ __global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __rest
   const int wv = tid >> 6;
   const int t = lane % TILE;
   const bool own = lane < TILE;
-  const int pb = __builtin_amdgcn_readfirstlane(tb.split[wv]);
-  const int pe = __builtin_amdgcn_readfirstlane(tb.split[wv + 1]);
+  // pairs are sorted by coupling type and dealt round-robin, so all waves of a block run
+  // the same specialised code at about the same time
+  const int pb = __builtin_amdgcn_readfirstlane(wv);
   // ------------------------------------------------------------ energy pass
   Acc<T> acc{T(0), T(0), T(0), T(0)};
   if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
-  for (int pi = pb; pi < pe; ++pi) {
+  for (int pi = pb; pi < npairs; pi += NW) {
     const int* rec = tb.pairs + pi * kPairRec;
     const int type = __builtin_amdgcn_readfirstlane(rec[2]);
 #define APX_FWD(A_, B_) \
@@ -477,7 +526,7 @@ __global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __rest
   __syncthreads();
   if (wv == 0 && own) {
     T s1 = T(0), e1 = T(0), s2 = T(0), e2 = T(0);
-    for (int v = 0; v < kAceWaves; ++v) {
+    for (int v = 0; v < NW; ++v) {
       acc_add<T, COMP>(s1, e1, T(1), red[(v * 4 + 0) * TILE + t]);
       e1 += red[(v * 4 + 1) * TILE + t];
       acc_add<T, COMP>(s2, e2, T(1), red[(v * 4 + 2) * TILE + t]);
@@ -502,7 +551,7 @@ __global__ void __launch_bounds__(kAceWaves * 64) k_ace_products(const T* __rest
     }
   }
   if (wv == 0) low_order_bwd<T, TILE, DC>(As, Ab, tb, nb1, nb2, t, own, fp, wdc, wfp, dc1, dc2);
-  for (int pi = pb; pi < pe; ++pi) {
+  for (int pi = pb; pi < npairs; pi += NW) {
     const int* rec = tb.pairs + pi * kPairRec;
     const int type = __builtin_amdgcn_readfirstlane(rec[2]);
 #define APX_BWD(A_, B_)                                                                                   \
@@ -540,14 +589,17 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   const int lane = threadIdx.x;
   const int i = active[q];
   const double wi = w ? w[i] : 1.0;
-  const T* Abr = sc.Ab + (size_t)q * K * LM;
+  const int na = K * LM;
+  const int ts = sc.tile_size;
+  const T* Abr = ts > 0 ? sc.Ab + (size_t)(q / ts) * na * ts + (q % ts) : sc.Ab + (size_t)q * na;
+  const int as = ts > 0 ? ts : 1;
   // back-projection: Ab2[k][lm] = sum_n Wp[l][n][k] Abar[n][lm]
   for (int o = lane; o < K * LM; o += 64) {
     const int kk = o / LM, lm = o - kk * LM;
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
     T v = T(0);
-    for (int nn = 0; nn < K; ++nn) v += Wp[((size_t)l * K + nn) * K + kk] * Abr[nn * LM + lm];
+    for (int nn = 0; nn < K; ++nn) v += Wp[((size_t)l * K + nn) * K + kk] * Abr[(size_t)(nn * LM + lm) * as];
     Ab2[o] = v;
   }
   __syncthreads();
@@ -651,6 +703,261 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   }
 }
 
+// ------------------------------------------------- kernel 2b (float32, unit adjoint)
+// Same energy pass as k_ace_products; the adjoint is reorganised so that no LDS atomics
+// are needed.  The adjoint work is cut into units (l1, l2, L): all pairs of one coupling
+// type, restricted to third blocks of degree L.  A unit is owned by one wave, which keeps
+//   acc3[n3][M]  the adjoint of every third block (n3, L)            (registers)
+//   accR[m]      the adjoint of the pair label with the larger degree, accumulated over
+//                the run of pairs sharing it (pairs are sorted by it)
+// and adds them to the tile's adjoint in global memory with float atomics when a run or
+// the unit ends; the adjoint of the other pair label is added per pair.
+template <class T, int TILE>
+__device__ __forceinline__ void gadd(T* __restrict__ Abt, int a, int t, T v, bool own) {
+  if (own) unsafeAtomicAdd(&Abt[(size_t)a * TILE + t], v);
+}
+
+template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
+__device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
+                                         int pb, int pe, int half, int n_max, int t, bool own, T fp) {
+  using C = Couple3<LMAX, L1, L2, L>;
+  constexpr int ST = TILE + 1;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  constexpr int N1 = 2 * L1 + 1, N2 = 2 * L2 + 1, NL = 2 * L + 1;
+  constexpr bool RUN1 = L1 >= L2;
+  constexpr int NR = RUN1 ? N1 : N2;
+  constexpr int NO = RUN1 ? N2 : N1;
+  constexpr int LR = RUN1 ? L1 : L2;
+  constexpr int LO = RUN1 ? L2 : L1;
+  // this unit covers the pairs whose smaller-degree label lies in one half of [0, n_max)
+  const int hn = (n_max + 1) / 2;
+  const int obase = half ? hn : 0;
+  const int oend = half ? n_max : hn;
+  T acc3[NMAX][NL];
+  T accR[NR];
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) {
+#pragma unroll
+    for (int m = 0; m < NL; ++m) acc3[n][m] = T(0);
+  }
+
+#pragma unroll
+  for (int m = 0; m < NR; ++m) accR[m] = T(0);
+  int run_n = -1;
+  for (int pi = pb; pi < pe; ++pi) {
+    const int* rec = tb.pairs + pi * kPairRec;
+    const int q0 = __builtin_amdgcn_readfirstlane(rec[4 + L]);
+    const int q1 = __builtin_amdgcn_readfirstlane(rec[5 + L]);
+    if (q0 == q1) continue;
+    const int n1 = __builtin_amdgcn_readfirstlane(rec[3]);
+    const int n2 = __builtin_amdgcn_readfirstlane(rec[15]);
+    const int nrun = RUN1 ? n1 : n2;
+    const int noth = RUN1 ? n2 : n1;
+    if (noth < obase || noth >= oend) continue;
+    if (nrun != run_n) {
+      if (run_n >= 0) {
+#pragma unroll
+        for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m], own);
+      }
+#pragma unroll
+      for (int m = 0; m < NR; ++m) accR[m] = T(0);
+      run_n = nrun;
+    }
+    const int o1 = rec[0], o2 = rec[1];
+    const int n30 = __builtin_amdgcn_readfirstlane((rec[10 + L] - L * L) / P2);
+    T a[N1], b[N2], P[NL], Pb[NL];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) a[m] = As[(o1 + m) * ST + t];
+#pragma unroll
+    for (int m = 0; m < N2; ++m) b[m] = As[(o2 + m) * ST + t];
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+      P[m] = T(0);
+      Pb[m] = T(0);
+    }
+    C::template fwd<T>(a, b, P);
+#pragma unroll
+    for (int n3 = 0; n3 < NMAX; ++n3) {
+      if (n3 >= n30 && n3 < n_max) {
+        const Coef2<T> c = tb.tc[q0 + n3 - n30];
+        const T d = fma(fp, c.c2, c.c1);
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+          Pb[m] = fma(d, As[(n3 * P2 + L * L + m) * ST + t], Pb[m]);
+          acc3[n3][m] = fma(d, P[m], acc3[n3][m]);
+        }
+      }
+    }
+    T ga[N1], gb[N2];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) ga[m] = T(0);
+#pragma unroll
+    for (int m = 0; m < N2; ++m) gb[m] = T(0);
+    C::template bwd<T>(a, b, Pb, ga, gb);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) accR[m] += RUN1 ? ga[m] : gb[m];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, noth * P2 + LO * LO + m, t, RUN1 ? gb[m] : ga[m], own);
+  }
+  if (run_n >= 0) {
+#pragma unroll
+    for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m], own);
+  }
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) {
+    if (n < n_max) {
+#pragma unroll
+      for (int m = 0; m < NL; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m], own);
+    }
+  }
+}
+
+// B1 and B2 adjoint.  B2 entries are stored in catalogue order (n1, n2 >= n1, l); for
+// each (n1, l) the adjoint of block (n1, l) is accumulated over n2 in registers, the
+// adjoint of block (n2, l) is added to global memory per entry.
+template <class T, int LMAX, int TILE>
+__device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
+                                               int nb1, int n_max, int t, bool own, T fp) {
+  constexpr int ST = TILE + 1;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  for (int e = 0; e < nb1; ++e) gadd<T, TILE>(Abt, tb.b1_off[e], t, fma(fp, tb.b1_c2[e], tb.b1_c1[e]), own);
+  int base = 0;
+  for (int n1 = 0; n1 < n_max; ++n1) {
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      T accR[2 * l + 1];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) accR[m] = T(0);
+      for (int n2 = n1; n2 < n_max; ++n2) {
+        const int e = base + (n2 - n1) * (LMAX + 1) + l;
+        const T d = fma(fp, tb.b2_c2[e], tb.b2_c1[e]);
+        const int o1 = n1 * P2 + l * l, o2 = n2 * P2 + l * l;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
+          accR[m] = fma(d, x2, accR[m]);
+          gadd<T, TILE>(Abt, o2 + m, t, d * x1, own);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m], own);
+    }
+    base += (n_max - n1) * (LMAX + 1);
+  }
+}
+
+// coupled degree triples (l1, l2, L) for l_max 3 and 4
+#define APX_UNIT_CASES_3(X) \
+  X(0, 0, 0) X(0, 1, 1) X(0, 2, 2) X(0, 3, 3) X(1, 0, 1) X(1, 1, 0) X(1, 1, 2) X(1, 2, 1) \
+  X(1, 2, 3) X(1, 3, 2) X(2, 0, 2) X(2, 1, 1) X(2, 1, 3) X(2, 2, 0) X(2, 2, 2) X(2, 3, 1) \
+  X(2, 3, 3) X(3, 0, 3) X(3, 1, 2) X(3, 2, 1) X(3, 2, 3) X(3, 3, 0) X(3, 3, 2)
+#define APX_UNIT_CASES_4(X) \
+  X(0, 0, 0) X(0, 1, 1) X(0, 2, 2) X(0, 3, 3) X(0, 4, 4) X(1, 0, 1) X(1, 1, 0) X(1, 1, 2) \
+  X(1, 2, 1) X(1, 2, 3) X(1, 3, 2) X(1, 3, 4) X(1, 4, 3) X(2, 0, 2) X(2, 1, 1) X(2, 1, 3) \
+  X(2, 2, 0) X(2, 2, 2) X(2, 2, 4) X(2, 3, 1) X(2, 3, 3) X(2, 4, 2) X(2, 4, 4) X(3, 0, 3) \
+  X(3, 1, 2) X(3, 1, 4) X(3, 2, 1) X(3, 2, 3) X(3, 3, 0) X(3, 3, 2) X(3, 3, 4) X(3, 4, 1) \
+  X(3, 4, 3) X(4, 0, 4) X(4, 1, 3) X(4, 2, 2) X(4, 2, 4) X(4, 3, 1) X(4, 3, 3) X(4, 4, 0) \
+  X(4, 4, 2) X(4, 4, 4)
+
+template <class T, int LMAX, int NMAX, int TILE, int NW, bool COMP>
+__global__ void __launch_bounds__(NW * 64, 2) k_ace_products_units(const T* __restrict__ Ag, T* __restrict__ Abg,
+                                                                int n_act, int na, int n_max, AceTables<T> tb,
+                                                                int nb1, int nb2, T eps,
+                                                                const double* __restrict__ e_anch,
+                                                                const int* __restrict__ active,
+                                                                double* __restrict__ e_site) {
+  constexpr int ST = TILE + 1;
+  extern __shared__ double smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* red = As + (size_t)na * ST;  // [NW][4][TILE]
+  T* fps = red + NW * 4 * TILE;   // [TILE]
+  const int tid = threadIdx.x;
+  const int nthr = NW * 64;
+  const int q0 = blockIdx.x * TILE;
+  for (int e = tid; e < TILE * na; e += nthr) {
+    const int t = e / na, a = e - t * na;
+    const int q = q0 + t;
+    As[a * ST + t] = q < n_act ? Ag[(size_t)q * na + a] : T(0);
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int t = lane % TILE;
+  const bool own = lane < TILE && q0 + t < n_act;
+  // ------------------------------------------------------------ energy pass
+  Acc<T> acc{T(0), T(0), T(0), T(0)};
+  if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
+  for (int pi = wv; pi < tb.npairs; pi += NW) {
+    const int* rec = tb.pairs + pi * kPairRec;
+    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+#define APX_FWD(A_, B_) \
+  case A_ * (LMAX + 1) + B_: pair_fwd_n<T, LMAX, NMAX, TILE, COMP, A_, B_>(As, rec, tb, t, n_max, acc); break;
+    if constexpr (LMAX == 3) {
+      switch (type) { APX_PAIR_CASES_3(APX_FWD) default: break; }
+    } else {
+      switch (type) { APX_PAIR_CASES_4(APX_FWD) default: break; }
+    }
+#undef APX_FWD
+  }
+  if (lane < TILE) {
+    red[(wv * 4 + 0) * TILE + t] = acc.s1;
+    red[(wv * 4 + 1) * TILE + t] = acc.e1;
+    red[(wv * 4 + 2) * TILE + t] = acc.s2;
+    red[(wv * 4 + 3) * TILE + t] = acc.e2;
+  }
+  __syncthreads();
+  if (wv == 0 && lane < TILE) {
+    T s1 = T(0), e1 = T(0), s2 = T(0), e2 = T(0);
+    for (int v = 0; v < NW; ++v) {
+      acc_add<T, COMP>(s1, e1, T(1), red[(v * 4 + 0) * TILE + t]);
+      e1 += red[(v * 4 + 1) * TILE + t];
+      acc_add<T, COMP>(s2, e2, T(1), red[(v * 4 + 2) * TILE + t]);
+      e2 += red[(v * 4 + 3) * TILE + t];
+    }
+    T dfdx;
+    const T f2 = feps<T>(s2 + e2, eps, dfdx);
+    fps[t] = dfdx;
+    const int q = q0 + t;
+    if (q < n_act) e_site[active[q]] = (double)(s1 + e1) + (double)f2 + e_anch[q];
+  }
+  __syncthreads();
+  // ----------------------------------------------------------- adjoint units
+  const T fp = fps[t];
+  T* Abt = Abg + (size_t)blockIdx.x * na * TILE;
+  const int ub = __builtin_amdgcn_readfirstlane(tb.wave_units[wv]);
+  const int ue = __builtin_amdgcn_readfirstlane(tb.wave_units[wv + 1]);
+  for (int k = ub; k < ue; ++k) {
+    const int u = __builtin_amdgcn_readfirstlane(tb.wave_units[NW + 1 + k]);
+    const int* ur = tb.units + u * kUnitRec;
+    const int type = __builtin_amdgcn_readfirstlane(ur[0]);
+    const int L = __builtin_amdgcn_readfirstlane(ur[1]);
+    const int pb = __builtin_amdgcn_readfirstlane(ur[2]);
+    const int pe = __builtin_amdgcn_readfirstlane(ur[3]);
+    const int half = __builtin_amdgcn_readfirstlane(ur[4]);
+    if (L < 0) {
+      low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, t, own, fp);
+      continue;
+    }
+    const int key = type * (LMAX + 1) + L;
+#define APX_UNIT(A_, B_, C_)                                                                              \
+  case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
+    unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, pb, pe, half, n_max, t, own, fp);              \
+    break;
+    if constexpr (LMAX == 3) {
+      switch (key) { APX_UNIT_CASES_3(APX_UNIT) default: break; }
+    } else {
+      switch (key) { APX_UNIT_CASES_4(APX_UNIT) default: break; }
+    }
+#undef APX_UNIT
+  }
+}
+
+template <class T>
+__global__ void k_fill_zero_t(T* __restrict__ p, long long m) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = T(0);
+}
+
 __global__ void k_fill_zero(double* __restrict__ p, long long m) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) p[i] = 0.0;
@@ -664,13 +971,17 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
   const int n = (int)atoms->n;
   const int na = m->na;
-  const size_t bytes_A = sizeof(T) * (size_t)n_act * na;
+  const long long n_pad = (long long)((n_act + TILE - 1) / TILE) * TILE;
+  const size_t bytes_A = sizeof(T) * (size_t)n_pad * na;
   APX_ALLOC(ctx, buf, 2 * bytes_A + 2 * sizeof(double) * (size_t)n_act + 256);
   AceScratch<T> sc;
   sc.A = buf.as<T>();
   sc.Ab = reinterpret_cast<T*>(reinterpret_cast<char*>(buf.p) + bytes_A);
   sc.e_anch = reinterpret_cast<double*>(reinterpret_cast<char*>(buf.p) + 2 * bytes_A);
   sc.fp_anch = sc.e_anch + n_act;
+  // float32 without coefficient gradients: unit adjoint with register accumulation
+  const bool use_units = sizeof(T) == 4 && dc1 == nullptr;
+  sc.tile_size = use_units ? TILE : 0;
   BoxDev b = make_box(atoms);
   AnchorDev an{};
   an.on = m->anchored;
@@ -686,24 +997,70 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   const T rc = (T)m->r_cut, inv_h = (T)(1.0 / m->h);
   const double rc2 = m->r_cut * m->r_cut;
   const size_t lds1 = sizeof(T) * (12 * 65 + LM * 65 + 12 * LM);
+  {
+  ProfScope ps(ctx, "ace.basis");
   k_ace_basis<T, LMAX><<<n_act, 64, lds1, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
                                                          n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc);
   APX_LAUNCH_CHECK(ctx);
-  const size_t lds2 = sizeof(T) * ((size_t)2 * na * (TILE + 1) + kAceWaves * 4 * TILE + TILE);
+  }
+  int lds_max = 0;
+  APX_HIP(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  if constexpr (sizeof(T) == 4) {
+  if (use_units) {
+    constexpr int NWU = kUnitWaves;
+    const size_t ldsu = sizeof(T) * ((size_t)na * (TILE + 1) + NWU * 4 * TILE + TILE);
+    if (ldsu > (size_t)lds_max)
+      return fail(ctx, APX_EINVAL, "ACE tile needs %zu bytes of LDS, the device allows %d (reduce n_max)", ldsu, lds_max);
+    const long long nab = n_pad * na;
+    {
+      ProfScope ps(ctx, "ace.zero");
+      k_fill_zero_t<T><<<blocks_for(nab, 256), 256, 0, ctx->stream>>>(sc.Ab, nab);
+      APX_LAUNCH_CHECK(ctx);
+    }
+    const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
+    ProfScope ps(ctx, "ace.products");
+    auto launch = [&](auto kern) -> apx_status {
+      APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsu));
+      kern<<<nblk, NWU * 64, ldsu, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
+                                                  sc.e_anch, active, e_site);
+      APX_LAUNCH_CHECK(ctx);
+      return APX_OK;
+    };
+    apx_status s;
+    if constexpr (LMAX == 3) {
+      s = m->n_max <= 8 ? launch(k_ace_products_units<T, 3, 8, TILE, NWU, true>)
+                        : launch(k_ace_products_units<T, 3, 12, TILE, NWU, true>);
+    } else {
+      s = m->n_max <= 10 ? launch(k_ace_products_units<T, 4, 10, TILE, NWU, true>)
+                         : launch(k_ace_products_units<T, 4, 12, TILE, NWU, true>);
+    }
+    if (s != APX_OK) return s;
+  }
+  }
+  if (!use_units) {
+  constexpr int NW = sizeof(T) == 4 ? kAceWaves32 : kAceWaves64;
+  const size_t lds2 = sizeof(T) * ((size_t)2 * na * (TILE + 1) + NW * 4 * TILE + TILE);
+  if (lds2 > (size_t)lds_max)
+    return fail(ctx, APX_EINVAL, "ACE tile needs %zu bytes of LDS, the device allows %d (reduce n_max)", lds2, lds_max);
   const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
+  {
+  ProfScope ps(ctx, "ace.products");
   if (dc1) {
-    auto kern = k_ace_products<T, LMAX, TILE, sizeof(T) == 4, true>;
+    auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, true>;
     APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-    kern<<<nblk, kAceWaves * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
-                                                      sc.e_anch, active, w, e_site, dc1, dc2);
+    kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                               sc.e_anch, active, w, e_site, dc1, dc2);
   } else {
-    auto kern = k_ace_products<T, LMAX, TILE, sizeof(T) == 4, false>;
+    auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, false>;
     APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-    kern<<<nblk, kAceWaves * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
-                                                      sc.e_anch, active, w, e_site, nullptr, nullptr);
+    kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                               sc.e_anch, active, w, e_site, nullptr, nullptr);
   }
   APX_LAUNCH_CHECK(ctx);
+  }
+  }
   const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
+  ProfScope ps(ctx, "ace.force");
   k_ace_force<T, LMAX><<<n_act, 64, lds3, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
                                                          n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc, w, f);
   APX_LAUNCH_CHECK(ctx);

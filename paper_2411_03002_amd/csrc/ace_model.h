@@ -5,18 +5,32 @@
 
 namespace apx {
 
-constexpr int kAceWaves = 8;     // waves per block in the product-basis kernel
-constexpr int kPairRec = 12;     // ints per pair record: off1, off2, type, pad, tb[8]
+// Waves per block of the product-basis kernel: 16 for float32 (<= 128 VGPRs), 8 for
+// float64 (<= 256 VGPRs).
+constexpr int kAceWaves32 = 16;
+constexpr int kAceWaves64 = 8;
+// ints per pair record: [0] off1, [1] off2, [2] type = l1*(l_max+1)+l2, [3] n1,
+// [4+L] first triple of degree L (L = 0..l_max+1, the last entry closes the list),
+// [10+L] atomic-base offset of the first third block of degree L, [15] n2.
+constexpr int kPairRec = 16;
+// Waves per block of the unit-adjoint product kernel (float32).
+constexpr int kUnitWaves = 4;
+// ints per adjoint unit record: type, L (-1: the B1/B2 unit), first pair, end pair,
+// half (0: smaller-degree label n < n_max/2 ... see the kernel), padding.
+constexpr int kUnitRec = 8;
+
+template <class T>
+struct alignas(2 * sizeof(T)) Coef2 {
+  T c1, c2;
+};
 
 // Pointers into one precision's copy of the tables.
 template <class T>
 struct AceTables {
   const T* Wp;        // [l_max+1][n_max][n_max], W[l][n][k] * N_l / s_a
-  const int* pairs;   // [npairs][kPairRec]
-  const int* t_off;   // [ntrip] A offset of the third block
+  const int* pairs;   // [npairs][kPairRec], sorted by type
   const int* t_v;     // [ntrip] basis index
-  const T* t_c1;      // [ntrip]
-  const T* t_c2;
+  const Coef2<T>* tc; // [ntrip + 1] (c1, c2) per triple, one padding entry
   const int* b1_off;  // [nb1]
   const int* b1_v;
   const T* b1_c1;
@@ -25,7 +39,9 @@ struct AceTables {
   const int* b2_v;
   const T* b2_c1;
   const T* b2_c2;
-  const int* split;   // [kAceWaves + 1] pair ranges per wave
+  int npairs;
+  const int* units;       // [nunits][kUnitRec]
+  const int* wave_units;  // [kUnitWaves + 1 + nunits]: offsets, then unit indices per wave
 };
 
 }  // namespace apx
@@ -35,10 +51,11 @@ struct apx_ace_model {
   int n_max = 0, l_max = 0, na = 0;
   long long n_basis = 0;
   int npairs = 0, ntrip = 0, nb1 = 0, nb2 = 0;
+  long long coupling_terms = 0, triple_width = 0;  // per-atom work counts
   double r_cut = 5.0, h = 0.5, s_a = 1.0, eps = 0.1;
   int anchored = 0;
   apx_eam_params anchor{};
-  apx::DevBuf ints;           // pairs, t_off, t_v, b1_off, b1_v, b2_off, b2_v, split
+  apx::DevBuf ints;           // pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units
   apx::DevBuf reals64, reals32;
   apx::AceTables<double> t64{};
   apx::AceTables<float> t32{};

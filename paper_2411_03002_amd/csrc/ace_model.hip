@@ -1,6 +1,9 @@
 // Host-side construction of the ACE coupling tables (basis catalogue, pair and triple
 // lists, per-wave work split) and their upload to the device.
+#include <algorithm>
+#include <array>
 #include <cmath>
+#include <tuple>
 #include <cstring>
 
 #include "ace_coupling_gen.h"
@@ -34,8 +37,9 @@ bool coupled(int l1, int l2, int l3) { return ((l1 + l2 + l3) % 2 == 0) && l3 >=
 
 struct Catalogue {
   long long n_basis = 0;
-  std::vector<int> pairs, t_off, t_v, b1_off, b1_v, b2_off, b2_v, split;
-  std::vector<long long> t_coef, b1_coef, b2_coef;  // index into the user's coefficient vector
+  std::vector<int> pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units;
+  int ntrip = 0;
+  long long coupling_terms = 0, triple_width = 0;
 };
 
 Catalogue build_catalogue(int n_max, int l_max) {
@@ -57,7 +61,12 @@ Catalogue build_catalogue(int n_max, int l_max) {
         c.b2_v.push_back((int)v++);
       }
   // B3: enumerate in catalogue order to assign basis indices, then regroup per pair by L
-  std::vector<double> cost;
+  struct PairTmp {
+    int rec[kPairRec];
+    std::vector<int> v;  // basis indices of its triples, in segment order
+    double cost;
+  };
+  std::vector<PairTmp> tmp;
   for (int p1 = 0; p1 < P; ++p1)
     for (int p2 = p1; p2 < P; ++p2) {
       const int l1 = p1 % LL, l2 = p2 % LL;
@@ -70,42 +79,109 @@ Catalogue build_catalogue(int n_max, int l_max) {
         ++found;
       }
       if (!found) continue;
-      int rec[kPairRec] = {0};
-      rec[0] = off(p1);
-      rec[1] = off(p2);
-      rec[2] = l1 * LL + l2;
-      double cst = 8.0 + (l_max == 4 ? terms_of<4>(l1, l2) : terms_of<3>(l1, l2));
-      int t = (int)c.t_off.size();
+      PairTmp pt{};
+      pt.rec[0] = off(p1);
+      pt.rec[1] = off(p2);
+      pt.rec[2] = l1 * LL + l2;
+      pt.rec[3] = p1 / LL;
+      pt.rec[15] = p2 / LL;
+      const int nterm = l_max == 4 ? terms_of<4>(l1, l2) : terms_of<3>(l1, l2);
+      c.coupling_terms += nterm;
+      pt.cost = 8.0 + nterm;
+      int t = 0;
       for (int L = 0; L < LL; ++L) {
-        rec[4 + L] = t;
-        for (auto& e : byL[L]) {
-          c.t_off.push_back(e.first);
-          c.t_v.push_back(e.second);
-          cst += 2 * L + 1 + 2;
+        pt.rec[4 + L] = t;
+        pt.rec[10 + L] = byL[L].empty() ? 0 : byL[L][0].first;
+        for (size_t e = 0; e < byL[L].size(); ++e) {
+          // third blocks of one degree are consecutive in n: offsets step by (l_max+1)^2
+          if (byL[L][e].first != pt.rec[10 + L] + (int)e * LL * LL) throw 1;
+          pt.v.push_back(byL[L][e].second);
+          pt.cost += 2 * L + 1 + 2;
+          c.triple_width += 2 * L + 1;
           ++t;
         }
       }
-      for (int L = LL; L < kPairRec - 4; ++L) rec[4 + L] = t;
-      c.pairs.insert(c.pairs.end(), rec, rec + kPairRec);
-      cost.push_back(cst);
+      for (int L = LL; L <= 5; ++L) pt.rec[4 + L] = t;
+      tmp.push_back(pt);
     }
   c.n_basis = v;
-  // contiguous split of the pair list over the waves; wave 0 also owns B1 and B2
+  // group the pairs by coupling type so that a wave stays in one specialisation for
+  // long runs of pairs (instruction-cache locality); within a type order them by the
+  // label of larger degree (the run label of the adjoint units), then the other label
+  auto key = [LL](const PairTmp& a) {
+    const int l1 = a.rec[2] / LL, l2 = a.rec[2] % LL;
+    const int run = l1 >= l2 ? a.rec[3] : a.rec[15];
+    const int oth = l1 >= l2 ? a.rec[15] : a.rec[3];
+    return std::make_tuple(a.rec[2], run, oth);
+  };
+  std::stable_sort(tmp.begin(), tmp.end(), [&](const PairTmp& a, const PairTmp& b) { return key(a) < key(b); });
+  std::vector<double> cost;
+  int base = 0;
+  for (auto& pt : tmp) {
+    for (int L = 0; L <= 5; ++L) pt.rec[4 + L] += base;
+    base += (int)pt.v.size();
+    c.pairs.insert(c.pairs.end(), pt.rec, pt.rec + kPairRec);
+    c.t_v.insert(c.t_v.end(), pt.v.begin(), pt.v.end());
+    cost.push_back(pt.cost);
+  }
+  c.ntrip = base;
+  // cost of the B1/B2 part
   double b12 = (double)n_max;
   for (size_t q = 0; q < c.b2_v.size(); ++q) b12 += 2 * c.b2_off[3 * q + 2] + 1 + 2;
-  double total = b12;
-  for (double x : cost) total += x;
-  const double target = total / kAceWaves;
-  c.split.assign(kAceWaves + 1, 0);
-  double acc = b12;
-  int w = 1;
-  const int np = (int)cost.size();
-  for (int q = 0; q < np && w < kAceWaves; ++q) {
-    acc += cost[q];
-    while (w < kAceWaves && acc >= w * target) c.split[w++] = q + 1;
+  // adjoint units (type, L) over the contiguous pair range of each type, plus one unit for
+  // B1/B2, dealt to the waves by longest processing time first
+  std::vector<std::array<int, kUnitRec>> units;
+  const int half_n = (n_max + 1) / 2;
+  std::vector<double> ucost;
+  {
+    int q = 0;
+    const int np = (int)tmp.size();
+    while (q < np) {
+      int e = q;
+      while (e < np && tmp[e].rec[2] == tmp[q].rec[2]) ++e;
+      const int type = tmp[q].rec[2];
+      const int l1 = type / LL, l2 = type % LL;
+      for (int L = 0; L < LL; ++L) {
+        if (!coupled(l1, l2, L)) continue;
+        for (int h = 0; h < 2; ++h) {
+          double cst = 0.0;
+          for (int k = q; k < e; ++k) {
+            const int noth = l1 >= l2 ? tmp[k].rec[15] : tmp[k].rec[3];
+            if ((noth < half_n) != (h == 0)) continue;
+            const int nt = tmp[k].rec[5 + L] - tmp[k].rec[4 + L];
+            if (nt > 0) cst += 40.0 + 6.0 * nt * (2 * L + 1) + 3.0 * (2 * l1 + 1) * (2 * l2 + 1);
+          }
+          if (cst > 0.0) {
+            units.push_back({type, L, q, e, h, 0, 0, 0});
+            ucost.push_back(cst + 30.0 * n_max * (2 * L + 1));
+          }
+        }
+      }
+      q = e;
+    }
+    units.push_back({0, -1, 0, 0, 0, 0, 0, 0});
+    ucost.push_back(b12 * 3.0 + 30.0 * n_max * LL * LL);
   }
-  while (w < kAceWaves) c.split[w++] = np;
-  c.split[kAceWaves] = np;
+  std::vector<int> order(units.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ucost[a] > ucost[b]; });
+  std::vector<std::vector<int>> per(kUnitWaves);
+  std::vector<double> load(kUnitWaves, 0.0);
+  for (int u : order) {
+    int best = 0;
+    for (int w = 1; w < kUnitWaves; ++w)
+      if (load[w] < load[best]) best = w;
+    per[best].push_back(u);
+    load[best] += ucost[u];
+  }
+  for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());
+  c.wave_units.assign(kUnitWaves + 1, 0);
+  for (int w = 0; w < kUnitWaves; ++w) c.wave_units[w + 1] = c.wave_units[w] + (int)per[w].size();
+  for (int w = 0; w < kUnitWaves; ++w) {
+    // within a wave, keep units of one type together
+    std::sort(per[w].begin(), per[w].end());
+    c.wave_units.insert(c.wave_units.end(), per[w].begin(), per[w].end());
+  }
   return c;
 }
 
@@ -116,14 +192,18 @@ using namespace apx;
 
 extern "C" int64_t apx_ace_num_basis(int32_t n_max, int32_t l_max) {
   if (n_max < 1 || n_max > 12 || (l_max != 3 && l_max != 4)) return -1;
-  return build_catalogue(n_max, l_max).n_basis;
+  try {
+    return build_catalogue(n_max, l_max).n_basis;
+  } catch (...) {
+    return -1;
+  }
 }
 
 template <class T>
 static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalogue& c, const double* c1,
                        const double* c2, size_t* offs) {
   const int LL = m->l_max + 1, nm = m->n_max;
-  // order: Wp, t_c1, t_c2, b1_c1, b1_c2, b2_c1, b2_c2
+  // order: Wp, (c1, c2) per triple + one padding pair, b1_c1, b1_c2, b2_c1, b2_c2
   out.clear();
   offs[0] = out.size();
   for (int l = 0; l < LL; ++l) {
@@ -131,10 +211,15 @@ static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalo
     for (int n = 0; n < nm; ++n)
       for (int k = 0; k < nm; ++k) out.push_back((T)(m->W[((size_t)l * nm + n) * nm + k] * nl / m->s_a));
   }
+  while (out.size() % 4) out.push_back((T)0);
   offs[1] = out.size();
-  for (int v : c.t_v) out.push_back((T)c1[v]);
+  for (int v : c.t_v) {
+    out.push_back((T)c1[v]);
+    out.push_back((T)c2[v]);
+  }
+  out.push_back((T)0);
+  out.push_back((T)0);
   offs[2] = out.size();
-  for (int v : c.t_v) out.push_back((T)c2[v]);
   offs[3] = out.size();
   for (int v : c.b1_v) out.push_back((T)c1[v]);
   offs[4] = out.size();
@@ -149,20 +234,19 @@ static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalo
 template <class T>
 static void set_tables(AceTables<T>& t, const T* base, const size_t* offs, const int* ib, const size_t* ioffs) {
   t.Wp = base + offs[0];
-  t.t_c1 = base + offs[1];
-  t.t_c2 = base + offs[2];
+  t.tc = reinterpret_cast<const Coef2<T>*>(base + offs[1]);
   t.b1_c1 = base + offs[3];
   t.b1_c2 = base + offs[4];
   t.b2_c1 = base + offs[5];
   t.b2_c2 = base + offs[6];
   t.pairs = ib + ioffs[0];
-  t.t_off = ib + ioffs[1];
-  t.t_v = ib + ioffs[2];
-  t.b1_off = ib + ioffs[3];
-  t.b1_v = ib + ioffs[4];
-  t.b2_off = ib + ioffs[5];
-  t.b2_v = ib + ioffs[6];
-  t.split = ib + ioffs[7];
+  t.t_v = ib + ioffs[1];
+  t.b1_off = ib + ioffs[2];
+  t.b1_v = ib + ioffs[3];
+  t.b2_off = ib + ioffs[4];
+  t.b2_v = ib + ioffs[5];
+  t.units = ib + ioffs[6];
+  t.wave_units = ib + ioffs[7];
 }
 
 extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, apx_ace_model** out) {
@@ -174,7 +258,12 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   if (!d->W || !d->c1 || !d->c2) return fail(ctx, APX_EINVAL, "W, c1 and c2 are required");
   if (!(d->r_cut > 0.0) || !(d->h > 0.0) || !(d->s_a > 0.0) || !(d->eps > 0.0))
     return fail(ctx, APX_EINVAL, "r_cut, h, s_a and eps must be positive");
-  Catalogue c = build_catalogue(d->n_max, d->l_max);
+  Catalogue c;
+  try {
+    c = build_catalogue(d->n_max, d->l_max);
+  } catch (...) {
+    return fail(ctx, APX_EINVAL, "inconsistent coupling catalogue");
+  }
   apx_ace_model* m = new apx_ace_model();
   m->device = ctx->device;
   m->n_max = d->n_max;
@@ -182,9 +271,11 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   m->na = d->n_max * (d->l_max + 1) * (d->l_max + 1);
   m->n_basis = c.n_basis;
   m->npairs = (int)(c.pairs.size() / kPairRec);
-  m->ntrip = (int)c.t_off.size();
+  m->ntrip = c.ntrip;
   m->nb1 = (int)c.b1_v.size();
   m->nb2 = (int)c.b2_v.size();
+  m->coupling_terms = c.coupling_terms;
+  m->triple_width = c.triple_width;
   m->r_cut = d->r_cut;
   m->h = d->h;
   m->s_a = d->s_a;
@@ -195,7 +286,7 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   // integer tables
   std::vector<int> ib;
   size_t ioffs[8];
-  const std::vector<int>* parts[8] = {&c.pairs, &c.t_off, &c.t_v, &c.b1_off, &c.b1_v, &c.b2_off, &c.b2_v, &c.split};
+  const std::vector<int>* parts[8] = {&c.pairs, &c.t_v, &c.b1_off, &c.b1_v, &c.b2_off, &c.b2_v, &c.units, &c.wave_units};
   for (int q = 0; q < 8; ++q) {
     ioffs[q] = ib.size();
     ib.insert(ib.end(), parts[q]->begin(), parts[q]->end());
@@ -219,7 +310,20 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   }
   set_tables(m->t64, m->reals64.as<double>(), o64, m->ints.as<int>(), ioffs);
   set_tables(m->t32, m->reals32.as<float>(), o32, m->ints.as<int>(), ioffs);
+  m->t64.npairs = m->npairs;
+  m->t32.npairs = m->npairs;
   *out = m;
+  return APX_OK;
+}
+
+extern "C" apx_status apx_ace_model_stats(const apx_ace_model* m, int64_t* out6) {
+  if (!m || !out6) return APX_EINVAL;
+  out6[0] = m->npairs;
+  out6[1] = m->ntrip;
+  out6[2] = m->coupling_terms;
+  out6[3] = m->triple_width;
+  out6[4] = m->n_basis;
+  out6[5] = m->na;
   return APX_OK;
 }
 

@@ -73,6 +73,7 @@ extern "C" apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const 
   const long long nb = n > 0 ? (n + kRedThreads * kRedPer - 1) / (kRedThreads * kRedPer) : 1;
   APX_ALLOC(ctx, ctx->dtmp, sizeof(double) * (size_t)(nb + 1));
   double* part = ctx->dtmp.as<double>();
+  ProfScope ps(ctx, "blend");
   if (n > 0) {
     k_blend<<<(unsigned)nb, kRedThreads, 0, ctx->stream>>>(n, w, e_eam, e_ace, f_eam, f_ace, e_site, f, part);
     APX_LAUNCH_CHECK(ctx);

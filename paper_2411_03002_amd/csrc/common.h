@@ -48,6 +48,18 @@ struct Grid {
 
 }  // namespace apx
 
+namespace apx {
+struct ProfPending {
+  int id;
+  hipEvent_t a, b;
+};
+struct ProfStat {
+  std::string name;
+  long long launches = 0;
+  double ms = 0.0;
+};
+}  // namespace apx
+
 struct apx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -56,6 +68,11 @@ struct apx_ctx {
   apx::DevBuf cell_id, cell_count, cell_start, cell_fill, cell_atoms;
   apx::DevBuf scan_tmp, flags, itmp, itmp2, dtmp, ace_buf;
   int* host_pinned = nullptr;  // small pinned staging area for readbacks
+  // optional per-kernel timing with HIP events on the context stream
+  bool prof = false;
+  std::vector<apx::ProfPending> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<apx::ProfStat> prof_stats;
 };
 
 namespace apx {
@@ -93,6 +110,34 @@ apx_status scan_exclusive(apx_ctx* ctx, const int* in, long long m, int* out);
 
 // Reads `count` ints from device memory into host memory (synchronising).
 apx_status read_ints(apx_ctx* ctx, const int* dev, int* host, int count);
+
+// Per-kernel timing: a scope records an event pair around the launches it encloses
+// when profiling is enabled on the context.
+int prof_id(apx_ctx* ctx, const char* name);
+hipEvent_t prof_event(apx_ctx* ctx);
+void prof_flush(apx_ctx* ctx, bool wait);
+
+struct ProfScope {
+  apx_ctx* ctx;
+  int id = -1;
+  hipEvent_t a = nullptr;
+  ProfScope(apx_ctx* c, const char* name) : ctx(c) {
+    if (ctx && ctx->prof) {
+      id = prof_id(ctx, name);
+      a = prof_event(ctx);
+      if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = prof_event(ctx);
+      if (b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->prof_pending.push_back({id, a, b});
+      }
+    }
+  }
+};
 
 inline unsigned int blocks_for(long long n, int threads) {
   return (unsigned int)((n + threads - 1) / threads);

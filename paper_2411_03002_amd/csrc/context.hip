@@ -209,11 +209,74 @@ apx_status read_ints(apx_ctx* ctx, const int* dev, int* host, int count) {
   return APX_OK;
 }
 
+int prof_id(apx_ctx* ctx, const char* name) {
+  for (size_t k = 0; k < ctx->prof_stats.size(); ++k)
+    if (ctx->prof_stats[k].name == name) return (int)k;
+  ctx->prof_stats.push_back(ProfStat{name, 0, 0.0});
+  return (int)ctx->prof_stats.size() - 1;
+}
+
+hipEvent_t prof_event(apx_ctx* ctx) {
+  if (!ctx->prof_pool.empty()) {
+    hipEvent_t e = ctx->prof_pool.back();
+    ctx->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Accumulates completed event pairs (all of them when `wait`).
+void prof_flush(apx_ctx* ctx, bool wait) {
+  if (ctx->prof_pending.empty()) return;
+  if (wait) (void)hipStreamSynchronize(ctx->stream);
+  size_t keep = 0;
+  for (size_t k = 0; k < ctx->prof_pending.size(); ++k) {
+    ProfPending& p = ctx->prof_pending[k];
+    if (!wait && hipEventQuery(p.b) != hipSuccess) {
+      ctx->prof_pending[keep++] = p;
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->prof_stats[p.id].ms += ms;
+      ctx->prof_stats[p.id].launches += 1;
+    }
+    ctx->prof_pool.push_back(p.a);
+    ctx->prof_pool.push_back(p.b);
+  }
+  ctx->prof_pending.resize(keep);
+}
+
 }  // namespace apx
 
 using namespace apx;
 
 extern "C" {
+
+apx_status apx_profile_enable(apx_ctx* ctx, int32_t on) {
+  if (!ctx) return APX_EINVAL;
+  prof_flush(ctx, true);
+  ctx->prof_stats.clear();
+  ctx->prof = on != 0;
+  return APX_OK;
+}
+
+int32_t apx_profile_count(apx_ctx* ctx) {
+  if (!ctx) return APX_EINVAL;
+  prof_flush(ctx, true);
+  return (int32_t)ctx->prof_stats.size();
+}
+
+apx_status apx_profile_entry(apx_ctx* ctx, int32_t k, const char** name, int64_t* launches, double* total_ms) {
+  if (!ctx || !name || !launches || !total_ms) return APX_EINVAL;
+  if (k < 0 || k >= (int32_t)ctx->prof_stats.size()) return fail(ctx, APX_EINVAL, "profile entry out of range");
+  *name = ctx->prof_stats[k].name.c_str();
+  *launches = ctx->prof_stats[k].launches;
+  *total_ms = ctx->prof_stats[k].ms;
+  return APX_OK;
+}
 
 const char* apx_version(void) { return "apx 0.1 gfx950"; }
 
@@ -244,6 +307,8 @@ void apx_ctx_destroy(apx_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  prof_flush(ctx, true);
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
 }

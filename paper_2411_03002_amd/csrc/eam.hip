@@ -126,9 +126,13 @@ apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
   if (n == 0) return APX_OK;
   BoxDev b = make_box(atoms);
   EamDev d = eam_dev(p);
+  {
+  ProfScope ps(ctx, "eam.density");
   k_eam_density<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb,
                                                              w, e_site, rho, ufp, u);
   APX_LAUNCH_CHECK(ctx);
+  }
+  ProfScope ps(ctx, "eam.force");
   k_eam_force<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb,
                                                            ufp, u, f);
   APX_LAUNCH_CHECK(ctx);

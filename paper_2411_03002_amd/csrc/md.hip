@@ -236,6 +236,7 @@ apx_status md_forces(apx_md* md, const double* pos, const double* w, double* f, 
     const double cy = md->p.ind_center[1] + t * md->p.ind_velocity[1];
     const double cz = md->p.ind_center[2] + t * md->p.ind_velocity[2];
     BoxDev b = make_box(&md->atoms);
+    ProfScope ps(ctx, "md.indenter");
     k_indenter<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, pos, f, b, cx, cy, cz, md->p.ind_radius,
                                                             md->p.ind_k, scal + 2);
   }
@@ -343,14 +344,18 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
   for (int64_t it = 0; it < n_steps; ++it) {
     APX_HIP(ctx, hipEventRecord(md->ev[0], ctx->stream));
     k_fill_d<<<1, 64, 0, ctx->stream>>>(1, scal + 3, 0.0);
+    {
+    ProfScope ps(ctx, "md.kick_drift");
     k_kick_drift<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, pos, vel, f, md->atoms.frozen, ck, md->p.dt, b,
                                                              md->lo_dev.as<double>(), md->xref.as<double>(),
                                                              reinterpret_cast<unsigned long long*>(scal + 3));
     APX_LAUNCH_CHECK(ctx);
+    }
     double maxd2 = 0.0;
     APX_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, scal + 3, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::memcpy(&maxd2, ctx->host_pinned, sizeof(double));
+    prof_flush(ctx, false);
     const double half_skin = 0.5 * md->p.skin;
     if (maxd2 > half_skin * half_skin) {
       apx_status s = md_rebuild(md, pos);
@@ -366,8 +371,11 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     }
     apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, true);
     if (s != APX_OK) return s;
+    {
+    ProfScope ps(ctx, "md.kick");
     k_kick<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, vel, f, md->atoms.frozen, ck);
     APX_LAUNCH_CHECK(ctx);
+    }
     APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
     APX_HIP(ctx, hipEventSynchronize(md->ev[5]));
     float ms = 0.f;

@@ -110,8 +110,12 @@ extern "C" apx_status apx_build_neighbors(apx_ctx* ctx, const apx_atoms* atoms, 
     return APX_OK;
   }
   Grid g = make_grid(atoms, r_list);
-  s = bin_atoms(ctx, atoms, g);
+  {
+    ProfScope ps(ctx, "nbr.bin");
+    s = bin_atoms(ctx, atoms, g);
+  }
   if (s != APX_OK) return s;
+  ProfScope ps(ctx, "nbr.build");
   k_build<<<blocks_for(n, kNbThreads), kNbThreads, 0, ctx->stream>>>(
       atoms->pos, n, g, ctx->cell_start.as<int>(), ctx->cell_atoms.as<int>(), r_list * r_list, nl->max_nb,
       nl->count, nl->idx, ctx->flags.as<int>());

@@ -247,9 +247,12 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   pd.csp_lo = p->csp_lo;
   pd.width = p->csp_hi - p->csp_lo;
   pd.rc2 = p->r_cut * p->r_cut;
+  {
+  ProfScope ps(ctx, "prec.csp");
   k_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, g, atoms->frozen, nl->count, nl->idx,
                                                      nl->max_nb, pd, w0_extra, csp, w0, w);
   APX_LAUNCH_CHECK(ctx);
+  }
   if (p->r_hi > 0.0) {
     APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
     APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * 4);
@@ -270,6 +273,7 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
       sd.rh2 = p->r_hi * p->r_hi;
       spread_stencil(gs, p->r_hi, sd);
       const long long threads = (long long)nsrc * kWave;
+      ProfScope ps(ctx, "prec.spread");
       k_spread<<<blocks_for(threads, 256), 256, 0, ctx->stream>>>(
           atoms->pos, n, gs, sd, ctx->itmp.as<int>(), nsrc, w0, atoms->frozen, ctx->cell_start.as<int>(),
           ctx->cell_atoms.as<int>(), reinterpret_cast<unsigned long long*>(w));
@@ -278,6 +282,7 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   }
   APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
   APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
+  ProfScope ps(ctx, "prec.compact");
   k_mask<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, mask, ctx->itmp.as<int>());
   APX_LAUNCH_CHECK(ctx);
   s = scan_exclusive(ctx, ctx->itmp.as<int>(), n, ctx->itmp2.as<int>());

@@ -43,6 +43,24 @@ class Context:
         s = torch.cuda.current_stream(self.torch_device).cuda_stream
         self.lib.apx_ctx_set_stream(self.h, C.c_void_p(s))
 
+    def profile(self, on: bool = True):
+        """Enables (and resets) per-kernel event timing."""
+        self._check(self.lib.apx_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total_ms)} accumulated since profile() (synchronises)."""
+        k = self.lib.apx_profile_count(self.h)
+        if k < 0:
+            self._check(k)
+        out = {}
+        for e in range(k):
+            name = C.c_char_p()
+            launches = C.c_int64()
+            ms = C.c_double()
+            self._check(self.lib.apx_profile_entry(self.h, e, C.byref(name), C.byref(launches), C.byref(ms)))
+            out[name.value.decode()] = (int(launches.value), float(ms.value))
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.apx_ctx_destroy(self.h)
@@ -213,6 +231,13 @@ class AceModel:
         h = C.c_void_p()
         ctx._check(ctx.lib.apx_ace_model_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
+
+    def stats(self) -> dict:
+        """Per-atom work counts of the coupling tables."""
+        arr = (C.c_int64 * 6)()
+        self.ctx._check(self.ctx.lib.apx_ace_model_stats(self.h, arr))
+        keys = ("pairs", "triples", "coupling_terms", "triple_width", "n_basis", "n_atomic_base")
+        return dict(zip(keys, (int(v) for v in arr)))
 
     def close(self):
         if getattr(self, "h", None):
