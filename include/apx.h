@@ -171,6 +171,9 @@ apx_status apx_ace_model_stats(const apx_ace_model* m, int64_t* out6);
 /* Copies the descriptor's arrays to the device and builds the coupling tables. */
 apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* desc, apx_ace_model** out);
 void apx_ace_model_destroy(apx_ace_model* m);
+/* Replaces the coefficient vectors c1, c2 (host [n_basis] each) of a model; used to
+ * differentiate with respect to the coefficients.  Synchronises the context stream. */
+apx_status apx_ace_model_set_coeffs(apx_ctx* ctx, apx_ace_model* m, const double* c1, const double* c2);
 
 /* Evaluate ACE for the atoms listed in `active` (device, n_active entries, distinct).
  * e_site[n] (overwritten): E_i^ACE at active atoms, 0 elsewhere.  f[3][n]

@@ -1,0 +1,72 @@
+"""ACE energy as a torch.autograd.Function whose backward is the library's adjoint.
+
+Forward: the weighted ACE energy sum_i w_i E_i^ACE over the given atoms (Sec. III A),
+evaluated by apx_ace_energy_forces.  Backward: the same call's adjoint outputs, the
+w-weighted forces (dE/dx = -F) and the coefficient gradients dE/dc1, dE/dc2, scaled by
+the incoming gradient.  No autograd graph of the basis is built: the adjoint is the
+hand-written kernel.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ops
+
+
+class AceRunner:
+    """Fixed setting of an ACE evaluation: context, model, box, weights, atom subset."""
+
+    def __init__(self, ctx: ops.Context, model: ops.AceModel, lo, hi, periodic, w=None, active=None,
+                 precision: str = "fp64", r_list: float = 5.5, max_nb: int = 96):
+        self.ctx, self.model = ctx, model
+        self.lo, self.hi, self.periodic = tuple(lo), tuple(hi), tuple(periodic)
+        self.w, self.active, self.precision = w, active, precision
+        self.r_list = r_list
+        self.max_nb = max_nb
+        self._coeffs = None
+
+    def sync_coeffs(self, c1: torch.Tensor, c2: torch.Tensor):
+        """Uploads c1, c2 to the model when they differ from the last uploaded values."""
+        a = c1.detach().to("cpu", torch.float64)
+        b = c2.detach().to("cpu", torch.float64)
+        if self._coeffs is None or not (torch.equal(a, self._coeffs[0]) and torch.equal(b, self._coeffs[1])):
+            self.model.set_coeffs(a.numpy(), b.numpy())
+            self._coeffs = (a.clone(), b.clone())
+
+
+class AceEnergy(torch.autograd.Function):
+    """E = sum_i w_i E_i^ACE(pos; c1, c2).  Inputs: pos [3, n] float64 (device), c1, c2
+    [n_basis] float64 (any device), runner.  Returns a 0-d float64 tensor."""
+
+    @staticmethod
+    def forward(ctx, pos, c1, c2, runner: AceRunner):
+        runner.sync_coeffs(c1, c2)
+        p = pos.detach().contiguous()
+        atoms = ops.DeviceAtoms(p, runner.lo, runner.hi, runner.periodic)
+        nl = ops.build_neighbors(runner.ctx, atoms, runner.r_list, max_nb=runner.max_nb)
+        n = p.shape[1]
+        active = runner.active
+        if active is None:
+            active = torch.arange(n, dtype=torch.int32, device=p.device)
+        want = bool(ctx.needs_input_grad[1] or ctx.needs_input_grad[2])
+        out = ops.ace_energy_forces(runner.ctx, atoms, nl, runner.model, active, runner.w, runner.precision,
+                                    want_dc=want)
+        w = runner.w if runner.w is not None else torch.ones(n, dtype=torch.float64, device=p.device)
+        e = (w * out["e_site"]).sum()
+        ctx.save_for_backward(out["f"], out.get("dE_dc1"), out.get("dE_dc2"))
+        ctx.c_devices = (c1.device, c2.device)
+        return e
+
+    @staticmethod
+    def backward(ctx, g):
+        f, d1, d2 = ctx.saved_tensors
+        gpos = -g * f if ctx.needs_input_grad[0] else None
+        g1 = (g * d1).to(ctx.c_devices[0]) if ctx.needs_input_grad[1] else None
+        g2 = (g * d2).to(ctx.c_devices[1]) if ctx.needs_input_grad[2] else None
+        return gpos, g1, g2, None
+
+
+def ace_energy(pos, c1, c2, runner: AceRunner):
+    return AceEnergy.apply(pos, c1, c2, runner)

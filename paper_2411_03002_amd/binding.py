@@ -86,6 +86,7 @@ PROTOTYPES = {
     "apx_ace_num_basis": (C.c_int64, [C.c_int32, C.c_int32]),
     "apx_ace_model_create": (C.c_int32, [_P, C.POINTER(AceDesc), C.POINTER(_P)]),
     "apx_ace_model_destroy": (None, [_P]),
+    "apx_ace_model_set_coeffs": (C.c_int32, [_P, _P, _P, _P]),
     "apx_ace_energy_forces": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), _P, _P, _P, C.c_int64,
                                           C.c_int32, _P, _P, _P, _P]),
     "apx_blend": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),

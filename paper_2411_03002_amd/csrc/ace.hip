@@ -963,6 +963,22 @@ __global__ void k_fill_zero(double* __restrict__ p, long long m) {
   if (i < m) p[i] = 0.0;
 }
 
+// hipFuncSetAttribute once per kernel (the dynamic LDS size is the same for every call
+// with a given model shape; the largest seen is kept)
+static apx_status ensure_lds(apx_ctx* ctx, const void* kern, size_t bytes) {
+  static std::vector<std::pair<const void*, size_t>> done;
+  for (auto& d : done)
+    if (d.first == kern && d.second >= bytes) return APX_OK;
+  APX_HIP(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  for (auto& d : done)
+    if (d.first == kern) {
+      d.second = bytes;
+      return APX_OK;
+    }
+  done.push_back({kern, bytes});
+  return APX_OK;
+}
+
 template <class T, int LMAX>
 apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m,
                    const AceTables<T>& tb, const double* w, const int* active, int n_act, double* e_site,
@@ -1018,9 +1034,9 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
     }
     const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
-    ProfScope ps(ctx, "ace.products");
     auto launch = [&](auto kern) -> apx_status {
-      APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsu));
+      if (ensure_lds(ctx, (const void*)kern, ldsu) != APX_OK) return APX_EDEVICE;
+      ProfScope ps(ctx, "ace.products");
       kern<<<nblk, NWU * 64, ldsu, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
                                                   sc.e_anch, active, e_site);
       APX_LAUNCH_CHECK(ctx);
@@ -1047,12 +1063,12 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   ProfScope ps(ctx, "ace.products");
   if (dc1) {
     auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, true>;
-    APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
     kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
                                                sc.e_anch, active, w, e_site, dc1, dc2);
   } else {
     auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, false>;
-    APX_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
     kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
                                                sc.e_anch, active, w, e_site, nullptr, nullptr);
   }

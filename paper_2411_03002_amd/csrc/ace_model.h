@@ -60,4 +60,5 @@ struct apx_ace_model {
   apx::AceTables<double> t64{};
   apx::AceTables<float> t32{};
   std::vector<double> W;      // host copy [l][n][k]
+  std::vector<int> t_v, b1_v, b2_v;  // basis index of every coefficient slot (host)
 };

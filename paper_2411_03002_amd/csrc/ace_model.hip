@@ -283,6 +283,9 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   m->anchored = d->anchored ? 1 : 0;
   m->anchor = d->anchor;
   m->W.assign(d->W, d->W + (size_t)(d->l_max + 1) * d->n_max * d->n_max);
+  m->t_v = c.t_v;
+  m->b1_v = c.b1_v;
+  m->b2_v = c.b2_v;
   // integer tables
   std::vector<int> ib;
   size_t ioffs[8];
@@ -313,6 +316,26 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   m->t64.npairs = m->npairs;
   m->t32.npairs = m->npairs;
   *out = m;
+  return APX_OK;
+}
+
+extern "C" apx_status apx_ace_model_set_coeffs(apx_ctx* ctx, apx_ace_model* m, const double* c1, const double* c2) {
+  if (!ctx) return APX_EINVAL;
+  if (!m || !c1 || !c2) return fail(ctx, APX_EINVAL, "model, c1 and c2 are required");
+  Catalogue c;
+  c.t_v = m->t_v;
+  c.b1_v = m->b1_v;
+  c.b2_v = m->b2_v;
+  std::vector<double> r64;
+  std::vector<float> r32;
+  size_t o64[8], o32[8];
+  fill_reals(r64, m, c, c1, c2, o64);
+  fill_reals(r32, m, c, c1, c2, o32);
+  if (r64.size() * sizeof(double) > m->reals64.bytes || r32.size() * sizeof(float) > m->reals32.bytes)
+    return fail(ctx, APX_EINVAL, "coefficient table size changed");
+  APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  APX_HIP(ctx, hipMemcpy(m->reals64.p, r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
+  APX_HIP(ctx, hipMemcpy(m->reals32.p, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice));
   return APX_OK;
 }
 

@@ -232,6 +232,15 @@ class AceModel:
         ctx._check(ctx.lib.apx_ace_model_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
 
+    def set_coeffs(self, c1, c2):
+        """Replaces c1, c2 (host float64 arrays of length n_basis)."""
+        c1 = np.ascontiguousarray(c1, dtype=np.float64)
+        c2 = np.ascontiguousarray(c2, dtype=np.float64)
+        if c1.size != self.n_basis or c2.size != self.n_basis:
+            raise ValueError("coefficient vectors must have n_basis entries")
+        self.ctx.bind_stream()
+        self.ctx._check(self.ctx.lib.apx_ace_model_set_coeffs(self.ctx.h, self.h, c1.ctypes.data, c2.ctypes.data))
+
     def stats(self) -> dict:
         """Per-atom work counts of the coupling tables."""
         arr = (C.c_int64 * 6)()
