@@ -111,11 +111,13 @@ typedef struct {
   int32_t n_nn;        /* N, even, 2..16 (12 for FCC) */
   int32_t n_buffer;    /* N_buffer, N + N_buffer <= 16 */
   int32_t switch_kind; /* 0 linear, 1 f_cut */
-  int32_t reserved;
+  int32_t flags;       /* APX_PREC_CSP_GIVEN: csp is an input, the CSP pass is skipped */
   double csp_lo, csp_hi; /* Angstrom^2 */
   double r_cut;          /* CSP candidate cutoff, <= nl->r_list */
   double r_lo, r_hi;     /* spreading radii, Angstrom */
 } apx_prec_params;
+
+#define APX_PREC_CSP_GIVEN 1
 
 /* Outputs (device, length n): csp, w0, w, mask (1 where w > 0); active receives the
  * indices with w > 0 in ascending order and *n_active (host, (sync)) their number.
@@ -237,10 +239,54 @@ apx_status apx_md_init(apx_md* md, const double* pos, double* f, double* w);
  * pos, vel (A/ps), f, w are device arrays updated in place. stats: host, (sync). */
 apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, double* f, double* w,
                            int64_t n_steps, apx_md_stats* stats);
+/* Switches the integrator's detection to the learned criterion combined with the
+ * centro-symmetry one (mlp NULL: back to the centro-symmetry criterion alone).  The
+ * network must outlive the integrator.  Adaptive mode only. */
+typedef struct apx_mlp apx_mlp;
+apx_status apx_md_set_mlp(apx_md* md, apx_mlp* mlp, double tau_lo, double tau_hi);
 /* Device timers of the last apx_verlet_step call, milliseconds summed over its steps:
  * out[0] half kick + drift + neighbour rebuilds, [1] weight updates, [2] EAM, [3] ACE,
  * [4] blend + indenter + half kick. */
 apx_status apx_md_timings(apx_md* md, double* out5);
+
+/* ------------------------------------------------ learned precision indicator */
+/* The detection argument of the switching function may be replaced by another criterion
+ * (Appendix B, after eq. lambda_1_i).  Learned criterion: a 4-64-64-64-1 tanh network on
+ * per-atom features [rho_EAM, min(CSP, 50), coordination (neighbours closer than 3.08 A),
+ * |F_EAM|] (inputs standardised with mu, sd) predicting log(|F_ACE - F_EAM| + 1e-3).
+ * Parameters (float32, APX_MLP_PARAMS values): W1 [64][4], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64][64], b3 [64], W4 [64], b4 [1]. */
+#define APX_MLP_PARAMS 8705
+apx_status apx_mlp_create(apx_ctx* ctx, const float* params /*host*/, const float* mu /*host [4]*/,
+                          const float* sd /*host [4]*/, apx_mlp** out);
+void apx_mlp_destroy(apx_mlp* m);
+apx_status apx_mlp_get_params(apx_ctx* ctx, const apx_mlp* m, float* params /*host; (sync)*/);
+/* Feature range seen in training (host [4] each); outside it the learned weight is 0. */
+apx_status apx_mlp_set_range(apx_mlp* m, const float* fmin, const float* fmax);
+/* feat [n][4] float32 from rho [n], csp [n] and the unweighted EAM force f_eam [3][n]. */
+apx_status apx_features(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const double* rho,
+                        const double* csp, const double* f_eam, float* feat);
+/* float32 forward: out [n]. */
+apx_status apx_mlp_forward(apx_ctx* ctx, const apx_mlp* m, const float* feat, int64_t n, float* out);
+/* Gradient of the mean squared error over the nb samples sel[0..nb) (sel NULL: 0..nb-1)
+ * of feat/target: grad [APX_MLP_PARAMS] and *loss (device) overwritten. */
+apx_status apx_mlp_gradients(apx_ctx* ctx, apx_mlp* m, const float* feat, const float* target,
+                             const int32_t* sel, int64_t nb, float* grad, float* loss);
+/* Adam update of the parameters with grad (bias-corrected; the step counter is kept in m);
+ * grad is cleared. */
+apx_status apx_mlp_adam_step(apx_ctx* ctx, apx_mlp* m, const float* grad, float lr, float beta1,
+                             float beta2, float eps);
+/* One training step: gradients on the batch then Adam (lr, 0.9, 0.999, 1e-8); loss
+ * (device scalar, may be NULL) receives the batch mean squared error. */
+apx_status apx_mlp_train_step(apx_ctx* ctx, apx_mlp* m, const float* feat, const float* target,
+                              const int32_t* sel, int64_t nb, float lr, float* loss);
+/* Inference with bfloat16 weights and activations on the matrix cores, float32 sums. */
+apx_status apx_mlp_infer_bf16(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, float* out);
+/* pred [n] = bfloat16 inference; w0_extra [n] = 1 - f_cut((exp(pred) - 1e-3 - tau_lo) /
+ * (tau_hi - tau_lo)) for atoms inside the training feature range, 0 outside (those keep
+ * the centro-symmetry weight alone when combined by apx_compute_precision). */
+apx_status apx_mlp_precision(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, double tau_lo,
+                             double tau_hi, float* pred, double* w0_extra);
 
 #ifdef __cplusplus
 }

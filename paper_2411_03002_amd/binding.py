@@ -38,7 +38,7 @@ class NList(C.Structure):
 
 class PrecParams(C.Structure):
     _fields_ = [("n_nn", C.c_int32), ("n_buffer", C.c_int32), ("switch_kind", C.c_int32),
-                ("reserved", C.c_int32), ("csp_lo", C.c_double), ("csp_hi", C.c_double),
+                ("flags", C.c_int32), ("csp_lo", C.c_double), ("csp_hi", C.c_double),
                 ("r_cut", C.c_double), ("r_lo", C.c_double), ("r_hi", C.c_double)]
 
 
@@ -96,7 +96,21 @@ PROTOTYPES = {
     "apx_md_init": (C.c_int32, [_P, _P, _P, _P]),
     "apx_verlet_step": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int64, C.POINTER(MdStats)]),
     "apx_md_timings": (C.c_int32, [_P, C.POINTER(C.c_double)]),
+    "apx_md_set_mlp": (C.c_int32, [_P, _P, C.c_double, C.c_double]),
+    "apx_mlp_create": (C.c_int32, [_P, _P, _P, _P, C.POINTER(_P)]),
+    "apx_mlp_destroy": (None, [_P]),
+    "apx_mlp_get_params": (C.c_int32, [_P, _P, _P]),
+    "apx_mlp_set_range": (C.c_int32, [_P, _P, _P]),
+    "apx_features": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), _P, _P, _P, _P]),
+    "apx_mlp_forward": (C.c_int32, [_P, _P, _P, C.c_int64, _P]),
+    "apx_mlp_gradients": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int64, _P, _P]),
+    "apx_mlp_adam_step": (C.c_int32, [_P, _P, _P, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "apx_mlp_train_step": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int64, C.c_float, _P]),
+    "apx_mlp_infer_bf16": (C.c_int32, [_P, _P, _P, C.c_int64, _P]),
+    "apx_mlp_precision": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_double, C.c_double, _P, _P]),
 }
+MLP_PARAMS = 8705
+APX_PREC_CSP_GIVEN = 1
 
 _LIB = None
 

@@ -131,6 +131,9 @@ struct apx_md {
   DevBuf csp, w0, mask, active;
   DevBuf e_eam, e_ace, e_site, f_eam, f_ace, rho;
   DevBuf scal;  // [0] e_pot, [1] e_kin, [2] e_ind, [3] max displacement^2 bits
+  apx_mlp* mlp = nullptr;  // learned criterion (optional)
+  double tau_lo = 0.0, tau_hi = 0.0;
+  DevBuf feat, pred, w0x;
   hipEvent_t ev[6] = {};
   double t_acc[5] = {0, 0, 0, 0, 0};
 };
@@ -189,6 +192,32 @@ apx_status md_weights(apx_md* md, const double* pos, double* w) {
   apx_nlist nl;
   md_nlist(md, nl);
   int64_t na = 0;
+  if (md->mlp) {
+    // learned criterion: unweighted EAM (density, force), CSP without spreading, features,
+    // bfloat16 inference -> extra weight, then the full precision pass on the given CSP
+    apx_status s = apx_eam_forces(ctx, &md->atoms, &nl, &md->eam, nullptr, md->e_eam.as<double>(),
+                                  md->rho.as<double>(), md->f_eam.as<double>());
+    if (s != APX_OK) return s;
+    apx_prec_params p0 = md->prec;
+    p0.r_hi = 0.0;
+    p0.flags = 0;
+    s = apx_compute_precision(ctx, &md->atoms, &nl, &p0, nullptr, md->csp.as<double>(), md->w0.as<double>(), w,
+                              md->mask.as<uint8_t>(), md->active.as<int>(), &na);
+    if (s != APX_OK) return s;
+    s = apx_features(ctx, &md->atoms, &nl, md->rho.as<double>(), md->csp.as<double>(), md->f_eam.as<double>(),
+                     md->feat.as<float>());
+    if (s != APX_OK) return s;
+    s = apx_mlp_precision(ctx, md->mlp, md->feat.as<float>(), md->n, md->tau_lo, md->tau_hi, md->pred.as<float>(),
+                          md->w0x.as<double>());
+    if (s != APX_OK) return s;
+    apx_prec_params p1 = md->prec;
+    p1.flags = APX_PREC_CSP_GIVEN;
+    s = apx_compute_precision(ctx, &md->atoms, &nl, &p1, md->w0x.as<double>(), md->csp.as<double>(),
+                              md->w0.as<double>(), w, md->mask.as<uint8_t>(), md->active.as<int>(), &na);
+    if (s != APX_OK) return s;
+    md->n_active = na;
+    return APX_OK;
+  }
   apx_status s = apx_compute_precision(ctx, &md->atoms, &nl, &md->prec, nullptr, md->csp.as<double>(),
                                        md->w0.as<double>(), w, md->mask.as<uint8_t>(), md->active.as<int>(), &na);
   if (s != APX_OK) return s;
@@ -400,6 +429,22 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     st.e_indenter = h[2];
     st.n_active = md->n_active;
     *stats = st;
+  }
+  return APX_OK;
+}
+
+extern "C" apx_status apx_md_set_mlp(apx_md* md, apx_mlp* mlp, double tau_lo, double tau_hi) {
+  if (!md) return APX_EINVAL;
+  apx_ctx* ctx = md->ctx;
+  if (mlp && !(tau_hi > tau_lo)) return fail(ctx, APX_EINVAL, "tau_hi must exceed tau_lo");
+  if (mlp && md->p.mode != APX_MODE_ADAPTIVE) return fail(ctx, APX_EINVAL, "the learned criterion needs adaptive mode");
+  md->mlp = mlp;
+  md->tau_lo = tau_lo;
+  md->tau_hi = tau_hi;
+  if (mlp) {
+    APX_ALLOC(ctx, md->feat, sizeof(float) * 4 * (size_t)md->n);
+    APX_ALLOC(ctx, md->pred, sizeof(float) * (size_t)md->n);
+    APX_ALLOC(ctx, md->w0x, sizeof(double) * (size_t)md->n);
   }
   return APX_OK;
 }

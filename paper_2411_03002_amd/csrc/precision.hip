@@ -121,6 +121,25 @@ __global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int
   w[i] = v0;
 }
 
+// w0 and w from a given CSP (the CSP pass skipped).
+__global__ void k_switch(int n, const uint8_t* __restrict__ frozen, PrecDev p, const double* __restrict__ w0_extra,
+                         const double* __restrict__ csp, double* __restrict__ w0, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (frozen && frozen[i]) {
+    w0[i] = 0.0;
+    w[i] = 0.0;
+    return;
+  }
+  double v0 = switch_w0(csp[i], p);
+  if (w0_extra) {
+    const double e = w0_extra[i];
+    v0 = e > v0 ? e : v0;
+  }
+  w0[i] = v0;
+  w[i] = v0;
+}
+
 // Compacts the spreading sources (w0 > 0, not frozen) in any order.
 __global__ void k_sources(int n, const double* __restrict__ w0, const uint8_t* __restrict__ frozen,
                           int* __restrict__ src, int* __restrict__ nsrc) {
@@ -247,11 +266,15 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   pd.csp_lo = p->csp_lo;
   pd.width = p->csp_hi - p->csp_lo;
   pd.rc2 = p->r_cut * p->r_cut;
-  {
+  if (!(p->flags & APX_PREC_CSP_GIVEN)) {
   ProfScope ps(ctx, "prec.csp");
   k_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, g, atoms->frozen, nl->count, nl->idx,
                                                      nl->max_nb, pd, w0_extra, csp, w0, w);
   APX_LAUNCH_CHECK(ctx);
+  } else {
+    ProfScope ps(ctx, "prec.switch");
+    k_switch<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, w0, w);
+    APX_LAUNCH_CHECK(ctx);
   }
   if (p->r_hi > 0.0) {
     APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);

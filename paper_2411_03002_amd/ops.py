@@ -147,8 +147,9 @@ def build_neighbors(ctx: Context, atoms: DeviceAtoms, r_list: float, max_nb: int
     raise RuntimeError("unreachable")
 
 
-def prec_struct(p) -> B.PrecParams:
+def prec_struct(p, csp_given: bool = False) -> B.PrecParams:
     s = B.PrecParams()
+    s.flags = B.APX_PREC_CSP_GIVEN if csp_given else 0
     s.n_nn = int(getattr(p, "n_nn", 12))
     s.n_buffer = int(getattr(p, "n_buffer", 0))
     s.switch_kind = int(p.switch_kind)
@@ -168,17 +169,19 @@ def eam_struct(p) -> B.EamParams:
     return s
 
 
-def compute_precision(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w0_extra=None) -> dict:
+def compute_precision(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w0_extra=None,
+                      csp=None) -> dict:
+    """apx_compute_precision; with ``csp`` given the CSP pass is skipped and it is used."""
     ctx.bind_stream()
     n = atoms.n
     dev = atoms.pos.device
-    out = dict(csp=torch.empty(n, dtype=torch.float64, device=dev),
+    out = dict(csp=csp if csp is not None else torch.empty(n, dtype=torch.float64, device=dev),
                w0=torch.empty(n, dtype=torch.float64, device=dev),
                w=torch.empty(n, dtype=torch.float64, device=dev),
                mask=torch.empty(n, dtype=torch.uint8, device=dev),
                active=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
     na = C.c_int64(0)
-    a, s, pp = atoms.struct(), nl.struct(), prec_struct(params)
+    a, s, pp = atoms.struct(), nl.struct(), prec_struct(params, csp is not None)
     ctx._check(ctx.lib.apx_compute_precision(ctx.h, C.byref(a), C.byref(s), C.byref(pp), _p(w0_extra),
                                              _p(out["csp"]), _p(out["w0"]), _p(out["w"]), _p(out["mask"]),
                                              _p(out["active"]), C.byref(na)))
@@ -341,6 +344,12 @@ class MD:
                                                      C.byref(st)))
         return {k: getattr(st, k) for k, _ in B.MdStats._fields_}
 
+    def set_mlp(self, net, tau_lo: float, tau_hi: float):
+        """Learned criterion (None: centro-symmetry alone)."""
+        self.net = net
+        self.ctx._check(self.ctx.lib.apx_md_set_mlp(self.h, net.h if net is not None else None, float(tau_lo),
+                                                    float(tau_hi)))
+
     def timings(self) -> list:
         arr = (C.c_double * 5)()
         self.ctx._check(self.ctx.lib.apx_md_timings(self.h, arr))
@@ -349,6 +358,94 @@ class MD:
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.apx_md_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, rho, csp, f_eam) -> torch.Tensor:
+    """[n, 4] float32 features of the learned criterion."""
+    ctx.bind_stream()
+    feat = torch.empty((atoms.n, 4), dtype=torch.float32, device=atoms.pos.device)
+    a, s = atoms.struct(), nl.struct()
+    ctx._check(ctx.lib.apx_features(ctx.h, C.byref(a), C.byref(s), _p(rho), _p(csp), _p(f_eam), _p(feat)))
+    return feat
+
+
+class Mlp:
+    """Device copy of the learned criterion's network (apx_mlp_*)."""
+
+    N_PARAMS = B.MLP_PARAMS
+
+    def __init__(self, ctx: Context, params, mu, sd):
+        self.ctx = ctx
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.N_PARAMS:
+            raise ValueError("wrong parameter count")
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        sd = np.ascontiguousarray(sd, dtype=np.float32)
+        h = C.c_void_p()
+        ctx._check(ctx.lib.apx_mlp_create(ctx.h, p.ctypes.data, mu.ctypes.data, sd.ctypes.data, C.byref(h)))
+        self.h = h
+        self.loss = torch.zeros(1, dtype=torch.float32, device=ctx.torch_device)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.N_PARAMS, dtype=np.float32)
+        self.ctx.bind_stream()
+        self.ctx._check(self.ctx.lib.apx_mlp_get_params(self.ctx.h, self.h, out.ctypes.data))
+        return out
+
+    def set_range(self, fmin, fmax):
+        a = np.ascontiguousarray(fmin, dtype=np.float32)
+        b = np.ascontiguousarray(fmax, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.apx_mlp_set_range(self.h, a.ctypes.data, b.ctypes.data))
+
+    def forward(self, feat: torch.Tensor) -> torch.Tensor:
+        self.ctx.bind_stream()
+        out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        self.ctx._check(self.ctx.lib.apx_mlp_forward(self.ctx.h, self.h, _p(feat), feat.shape[0], _p(out)))
+        return out
+
+    def gradients(self, feat, target, sel=None):
+        self.ctx.bind_stream()
+        g = torch.empty(self.N_PARAMS, dtype=torch.float32, device=feat.device)
+        nb = int(sel.numel()) if sel is not None else int(feat.shape[0])
+        self.ctx._check(self.ctx.lib.apx_mlp_gradients(self.ctx.h, self.h, _p(feat), _p(target), _p(sel), nb,
+                                                       _p(g), _p(self.loss)))
+        return g, self.loss
+
+    def adam_step(self, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.ctx.bind_stream()
+        self.ctx._check(self.ctx.lib.apx_mlp_adam_step(self.ctx.h, self.h, _p(grad), lr, b1, b2, eps))
+
+    def train_step(self, feat, target, sel, lr=1e-3):
+        self.ctx.bind_stream()
+        self.ctx._check(self.ctx.lib.apx_mlp_train_step(self.ctx.h, self.h, _p(feat), _p(target), _p(sel),
+                                                        int(sel.numel()), lr, _p(self.loss)))
+        return self.loss
+
+    def infer_bf16(self, feat: torch.Tensor) -> torch.Tensor:
+        self.ctx.bind_stream()
+        out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        self.ctx._check(self.ctx.lib.apx_mlp_infer_bf16(self.ctx.h, self.h, _p(feat), feat.shape[0], _p(out)))
+        return out
+
+    def precision(self, feat: torch.Tensor, tau_lo: float, tau_hi: float):
+        self.ctx.bind_stream()
+        n = feat.shape[0]
+        pred = torch.empty(n, dtype=torch.float32, device=feat.device)
+        w0 = torch.empty(n, dtype=torch.float64, device=feat.device)
+        self.ctx._check(self.ctx.lib.apx_mlp_precision(self.ctx.h, self.h, _p(feat), n, float(tau_lo), float(tau_hi),
+                                                       _p(pred), _p(w0)))
+        return pred, w0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.apx_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -30,7 +30,9 @@ from .params import (  # noqa: F401
     PrecisionParams,
     eam_cu_like,
     eam_anchor,
+    eam_label_anchor,
     ace_random,
+    ace_label_model,
     precision_cfg0,
     precision_hyb1,
     precision_static,

@@ -75,8 +75,14 @@ def eam_anchor(a: float = A_CU) -> EamParams:
     return EamParams(A=0.14169266975963063, alpha=4.4, beta=1.75, r0=a / np.sqrt(2.0))
 
 
+def eam_label_anchor(a: float = A_CU) -> EamParams:
+    """EAM part of the label potential: one tenth of the way from the fast potential to
+    ``eam_anchor`` (alpha 4.31, beta 1.795), amplitude again chosen stress-free."""
+    return EamParams(A=0.14595440108128369, alpha=4.31, beta=1.795, r0=a / np.sqrt(2.0))
+
+
 def ace_random(n_max: int, l_max: int, n_basis: int, seed: int,
-               anchored: bool = False, coef_std: float = 0.01) -> AceParams:
+               anchored: bool = False, coef_std: float = 0.01, anchor: EamParams | None = None) -> AceParams:
     """Random-initialised ACE parameters.
 
     Draw order from ``default_rng(seed)``: W ~ N(0, 1/n_max) of shape
@@ -87,8 +93,18 @@ def ace_random(n_max: int, l_max: int, n_basis: int, seed: int,
     W = rng.normal(0.0, 1.0 / np.sqrt(n_max), size=(l_max + 1, n_max, n_max))
     c1 = rng.normal(0.0, coef_std, size=n_basis)
     c2 = rng.normal(0.0, coef_std, size=n_basis)
-    return AceParams(n_max=n_max, l_max=l_max, W=W, c1=c1, c2=c2,
-                     anchor=eam_anchor() if anchored else None)
+    if anchored and anchor is None:
+        anchor = eam_anchor()
+    return AceParams(n_max=n_max, l_max=l_max, W=W, c1=c1, c2=c2, anchor=anchor if anchored else None)
+
+
+def ace_label_model(n_basis: int, seed: int = 4242, coef_std: float = 1e-4) -> AceParams:
+    """Precise potential of the learned-indicator workload (n_max 10, l_max 4): an EAM part
+    whose force constants differ slightly from the fast potential's (``eam_label_anchor``)
+    plus a small random many-body part.  Both potentials hold the perfect lattice at the
+    same spacing, so their forces agree on the lattice and part the more, the further an
+    atom's surroundings are displaced, compressed or cut by a surface."""
+    return ace_random(10, 4, n_basis, seed, anchored=True, coef_std=coef_std, anchor=eam_label_anchor())
 
 
 def precision_cfg0() -> PrecisionParams:

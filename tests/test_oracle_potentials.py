@@ -71,7 +71,7 @@ def test_eam_perfect_lattice_closed_form():
     assert np.max(np.abs(ev["f"])) < 1e-12
 
 
-@pytest.mark.parametrize("maker", [synth.eam_cu_like, synth.eam_anchor])
+@pytest.mark.parametrize("maker", [synth.eam_cu_like, synth.eam_anchor, synth.eam_label_anchor])
 def test_eam_stress_free_at_a(maker):
     # the amplitudes were chosen for zero pressure at a = 3.615 A: dE/da = 0
     p = maker()
