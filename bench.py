@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-full", action="store_true", help="skip the full-ACE comparison")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the adaptive timed region (for external profilers)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a 1 GiB device-to-device copy (scales hardware byte counters)")
     return ap.parse_args()
 
 
@@ -133,6 +135,14 @@ def main():
     from paper_2411_03002_amd import ops
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.copy_calibration:
+        a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel(), "copy_bytes_written": b.numel()}), flush=True)
+        return
     K, W = args.steps, args.warmup
     KF = args.full_steps if args.full_steps is not None else K
     cells = args.cells
@@ -185,6 +195,7 @@ def main():
                                f"anchored ACE n_max 10 l_max 4 (float32), Hyb1 detection every 10 steps",
                    "atoms": n, "dt_fs": 1.0, "precision_every": 10},
         "active_atoms": int(st_a["n_active"]), "active_fraction": st_a["n_active"] / n,
+        "active_atoms_mean": st_a["ace_atoms"] / K,
         "rebuilds": int(st_a["rebuilds"]),
         "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
                                       [t / K for t in tim_a])),
@@ -194,7 +205,9 @@ def main():
         return
     # live per-kernel roofline of the adaptive timed region
     nb_avg = 60.0
-    models = kernel_models(stats, n, st_a["n_active"], nb_avg, 42.0)
+    # ACE work per launch: the mean number of atoms ACE was evaluated for over the timed
+    # steps (the detected set changes at every weight update)
+    models = kernel_models(stats, n, st_a["ace_atoms"] / K, nb_avg, 42.0)
     kern = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_a.items()}
     dom = max(prof_a.items(), key=lambda kv: kv[1][1])[0]
     result["kernels"] = kern
@@ -225,7 +238,7 @@ def main():
         result["full_ace_atom_steps_per_s"] = full
         result["full_ace_ms_per_step"] = dt_f / KF * 1e3
         result["adaptive_over_full_ace"] = adaptive / full
-        mf = kernel_models(stats, n, n, nb_avg, 42.0)
+        mf = kernel_models(stats, n, st_f["ace_atoms"] / KF, nb_avg, 42.0)
         if "ace.products" in prof_f:
             result["roofline_full_ace_products"] = roofline_for("ace.products", mf["ace.products"],
                                                                 *prof_f["ace.products"])

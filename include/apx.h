@@ -223,6 +223,7 @@ typedef struct {
   int64_t n_active;      /* atoms with w > 0 after the call */
   double e_pot, e_kin;   /* at the end of the call, eV (potential excludes the indenter) */
   double e_indenter;     /* indenter energy at the end, eV */
+  int64_t ace_atoms;     /* sum over the call's steps of the atoms ACE was evaluated for */
 } apx_md_stats;
 
 /* An integrator bound to a box, potentials and criterion.  `atoms` supplies n, box,

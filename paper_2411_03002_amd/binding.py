@@ -63,7 +63,7 @@ class MdParams(C.Structure):
 class MdStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("precision_updates", C.c_int64),
                 ("n_active", C.c_int64), ("e_pot", C.c_double), ("e_kin", C.c_double),
-                ("e_indenter", C.c_double)]
+                ("e_indenter", C.c_double), ("ace_atoms", C.c_int64)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/apx.h

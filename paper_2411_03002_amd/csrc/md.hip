@@ -400,6 +400,7 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     }
     apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, true);
     if (s != APX_OK) return s;
+    st.ace_atoms += md->n_active;
     {
     ProfScope ps(ctx, "md.kick");
     k_kick<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, vel, f, md->atoms.frozen, ck);
