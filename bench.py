@@ -47,6 +47,8 @@ def parse():
                     help="only the adaptive timed region (for external profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 1 GiB device-to-device copy (scales hardware byte counters)")
+    ap.add_argument("--learned", action="store_true",
+                    help="the learned-indicator workload instead: train on 200 snapshots, deploy in the void run")
     return ap.parse_args()
 
 
@@ -64,13 +66,17 @@ def kernel_models(stats, n, n_act, nb_avg, nb_act_avg):
     Tc, Tw, Nt = stats["coupling_terms"], stats["triple_width"], stats["triples"]
     # energy: coupling 3/term, triples 2 per (2L+1) and 4 per triple; adjoint: coupling
     # recompute 3/term and back-propagation 5/term, triples 4 per (2L+1) and 2 per triple
-    f_products = 11.0 * Tc + 6.0 * Tw + 6.0 * Nt
+    f_energy = 3.0 * Tc + 2.0 * Tw + 4.0 * Nt
+    f_adjoint = 8.0 * Tc + 4.0 * Tw + 2.0 * Nt
+    f_products = f_energy + f_adjoint
     K, LM = 10, 25
     f_basis = nb_act_avg * (3 * K + 4 * LM + 2 * K * LM) + 2.0 * K * stats["n_atomic_base"]
     f_force = 2.0 * K * stats["n_atomic_base"] + nb_act_avg * (4 * K * LM + 12 * LM + 6 * K)
     row = 4.0 + 4.0 * nb_avg
     return {
-        "ace.products": ("mfma_free_alu_fp32", n_act * f_products, "flop"),
+        "ace.products": ("alu_fp32", n_act * f_products, "flop"),
+        "ace.energy": ("alu_fp32", n_act * f_energy, "flop"),
+        "ace.adjoint": ("alu_fp32", n_act * f_adjoint, "flop"),
         "ace.basis": ("alu_fp32", n_act * f_basis, "flop"),
         "ace.force": ("alu_fp32", n_act * f_force, "flop"),
         "eam.density": ("hbm", n * (row + 24 + 8 + 32), "byte"),
@@ -124,6 +130,92 @@ def cpu_baseline(sample_cells=(8, 8, 100), budget_s=30.0):
             "active_fraction": float(pr["active"].size) / s.n, "seconds": dt}
 
 
+def run_learned(args):
+    """Learned precision indicator: 200 method-generated 16,384-atom snapshots (bulk, 1 %
+    vacancies, 8 A void, (100) slab at 300-1200 K; 180 train / 20 validation), 20 epochs of
+    Adam (batch 4096, lr 1e-3) with the library's kernels, then the 130,445-atom void run
+    (100 steps, weights every 10) with the centro-symmetry criterion and with the learned
+    criterion: atom-steps/s of each, and misassigned atoms and force errors of both
+    criteria on the same configuration (the state after the centro-symmetry run)."""
+    import torch
+    import synth
+    from synth import configs
+    from paper_2411_03002_amd import learned, ops
+
+    tau_lo, tau_hi = 5e-3, 1e-2
+    ctx = ops.Context(0)
+    eam = synth.eam_cu_like()
+    model = ops.AceModel(ctx, synth.ace_label_model(ops.num_basis(10, 4)))
+    prec = synth.precision_hyb1()
+    t0 = time.perf_counter()
+    feats, labels = [], []
+    for k in range(200):
+        snap = learned.snapshot(ctx, configs.cfg4_snapshot(k), eam, model, prec, "fp32")
+        feats.append(snap.feat)
+        labels.append(snap.label)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    tr_f, tr_y = torch.cat(feats[:180]), torch.cat(labels[:180])
+    va_f, va_y = torch.cat(feats[180:]), torch.cat(labels[180:])
+    log(f"{tr_f.shape[0]} training and {va_f.shape[0]} validation samples in {t_data:.1f} s")
+    t0 = time.perf_counter()
+    net = learned.train(ctx, tr_f, tr_y, epochs=20, batch=4096, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    r_val = float(torch.corrcoef(torch.stack([net.infer_bf16(va_f), va_y]))[0, 1].item())
+    log(f"trained in {t_train:.1f} s, validation correlation (bf16 inference) {r_val:.3f}")
+
+    s = configs.cfg1()
+    atoms = ops.device_atoms(s)
+    vel0 = torch.as_tensor(s.vel, device="cuda").contiguous()
+    K, W = args.steps, args.warmup
+    runs = {}
+    for name in ("csp", "learned"):
+        md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
+                    ace_precision="fp32", mode="adaptive")
+        if name == "learned":
+            md.set_mlp(net, tau_lo, tau_hi)
+        pos, vel = atoms.pos.clone(), vel0.clone()
+        f, w = md.init(pos)
+        if W:
+            md.step(pos, vel, f, w, W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = md.step(pos, vel, f, w, K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        md.close()
+        runs[name] = {"atom_steps_per_s": s.n * K / dt, "ms_per_step": dt / K * 1e3,
+                      "active_mean": st["ace_atoms"] / K, "pos": pos}
+        log(f"{name}: {dt / K * 1e3:.3f} ms/step, mean detected {st['ace_atoms'] / K:.0f}")
+    # both criteria on the configuration the centro-symmetry run ended in
+    at = ops.DeviceAtoms(runs["csp"]["pos"], atoms.lo, atoms.hi, atoms.periodic, atoms.frozen)
+    nl = ops.build_neighbors(ctx, at, 5.5)
+    everyone = torch.arange(s.n, dtype=torch.int32, device="cuda")
+    f_ace = ops.ace_energy_forces(ctx, at, nl, model, everyone, None, "fp64")["f"]
+    dF = (f_ace - ops.eam_forces(ctx, at, nl, eam, None)["f"]).norm(dim=0)
+    assess = {}
+    for name, use in (("csp", None), ("learned", net)):
+        pr = learned.weights(ctx, at, nl, prec, eam, use, tau_lo, tau_hi)
+        e = ops.eam_forces(ctx, at, nl, eam, pr["w"])
+        a = ops.ace_energy_forces(ctx, at, nl, model, pr["active"], pr["w"], "fp64")
+        assess[name] = learned.assess(pr["w"], dF, e["f"] + a["f"], f_ace, tau_lo, tau_hi)
+    result = {
+        "metric": "learned vs CSP criterion: atom-steps/s and misassigned-atom force error", "unit": "atom-steps/s",
+        "value": runs["learned"]["atom_steps_per_s"], "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": runs["learned"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 ACE / f64 EAM; bf16 network inference", "data": "synthetic",
+        "config": {"workload": f"void run 32^3 FCC cells ({s.n} atoms, 12 A void, 300 K), label ACE "
+                               f"(n_max 10, l_max 4), Hyb1 detection every 10 steps; network trained on "
+                               f"200 x 16,384-atom snapshots", "atoms": s.n},
+        "training": {"samples": int(tr_f.shape[0]), "validation_samples": int(va_f.shape[0]),
+                     "data_seconds": t_data, "train_seconds": t_train, "validation_r_bf16": r_val},
+        "csp": {k: v for k, v in runs["csp"].items() if k != "pos"} | {"assessment": assess["csp"]},
+        "learned": {k: v for k, v in runs["learned"].items() if k != "pos"} | {"assessment": assess["learned"]},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -135,6 +227,9 @@ def main():
     from paper_2411_03002_amd import ops
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.learned:
+        run_learned(args)
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -239,9 +334,9 @@ def main():
         result["full_ace_ms_per_step"] = dt_f / KF * 1e3
         result["adaptive_over_full_ace"] = adaptive / full
         mf = kernel_models(stats, n, st_f["ace_atoms"] / KF, nb_avg, 42.0)
-        if "ace.products" in prof_f:
-            result["roofline_full_ace_products"] = roofline_for("ace.products", mf["ace.products"],
-                                                                *prof_f["ace.products"])
+        for k in ("ace.energy", "ace.adjoint"):
+            if k in prof_f:
+                result[f"roofline_full_ace_{k.split('.')[1]}"] = roofline_for(k, mf[k], *prof_f[k])
         result["kernels_full_ace"] = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
                                       for k, v in prof_f.items()}
         log(f"full ACE {dt_f / KF * 1e3:.2f} ms/step, {full:.4g} atom-steps/s, ratio {adaptive / full:.2f}")

@@ -38,6 +38,7 @@ struct AceScratch {
   int tile_size;
   double* e_anch;   // [n_act]
   double* fp_anch;  // [n_act]
+  T* fp;            // [tiles * tile_size] embedding slope F_eps'(phi2) per atom (float32 path)
 };
 
 // ------------------------------------------------------------ shared helpers
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
   T* gS = reinterpret_cast<T*>(smem_raw);  // [K][65]
   T* sS = gS + kMaxK * 65;                 // [LM][65]
   T* Ap = sS + LM * 65;                    // [K*LM]
-  const int q = blockIdx.x;
+  const int q = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   const int i = active[q];
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
@@ -585,7 +586,7 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   constexpr int kMaxK = 12;
   extern __shared__ double smem_raw[];
   T* Ab2 = reinterpret_cast<T*>(smem_raw);  // [K][LM]
-  const int q = blockIdx.x;
+  const int q = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   const int i = active[q];
   const double wi = w ? w[i] : 1.0;
@@ -712,14 +713,24 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
 //                the run of pairs sharing it (pairs are sorted by it)
 // and adds them to the tile's adjoint in global memory with float atomics when a run or
 // the unit ends; the adjoint of the other pair label is added per pair.
+// Every lane adds, padded lanes (beyond the last active atom) included: their slots lie
+// inside the tile's region and are never read back.
 template <class T, int TILE>
-__device__ __forceinline__ void gadd(T* __restrict__ Abt, int a, int t, T v, bool own) {
-  if (own) unsafeAtomicAdd(&Abt[(size_t)a * TILE + t], v);
+__device__ __forceinline__ void gadd(T* __restrict__ Abt, int a, int t, T v) {
+  unsafeAtomicAdd(&Abt[(size_t)a * TILE + t], v);
+}
+
+// Reads a read-only table entry (a scalar type) through the constant address space.  The adjoint kernels
+// store to global memory, so the compiler cannot prove their table reads unclobbered and
+// would issue vector loads; constant-space reads let it use scalar loads.
+template <class X>
+__device__ __forceinline__ X cld(const X* p) {
+  return *(const __attribute__((address_space(4))) X*)p;
 }
 
 template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
 __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                         int pb, int pe, int half, int n_max, int t, bool own, T fp) {
+                                         int pb, int pe, int half, int n_max, int t, T fp) {
   using C = Couple3<LMAX, L1, L2, L>;
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
@@ -746,25 +757,25 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   int run_n = -1;
   for (int pi = pb; pi < pe; ++pi) {
     const int* rec = tb.pairs + pi * kPairRec;
-    const int q0 = __builtin_amdgcn_readfirstlane(rec[4 + L]);
-    const int q1 = __builtin_amdgcn_readfirstlane(rec[5 + L]);
+    const int q0 = cld(rec + 4 + L);
+    const int q1 = cld(rec + 5 + L);
     if (q0 == q1) continue;
-    const int n1 = __builtin_amdgcn_readfirstlane(rec[3]);
-    const int n2 = __builtin_amdgcn_readfirstlane(rec[15]);
+    const int n1 = cld(rec + 3);
+    const int n2 = cld(rec + 15);
     const int nrun = RUN1 ? n1 : n2;
     const int noth = RUN1 ? n2 : n1;
     if (noth < obase || noth >= oend) continue;
     if (nrun != run_n) {
       if (run_n >= 0) {
 #pragma unroll
-        for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m], own);
+        for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m]);
       }
 #pragma unroll
       for (int m = 0; m < NR; ++m) accR[m] = T(0);
       run_n = nrun;
     }
-    const int o1 = rec[0], o2 = rec[1];
-    const int n30 = __builtin_amdgcn_readfirstlane((rec[10 + L] - L * L) / P2);
+    const int o1 = cld(rec), o2 = cld(rec + 1);
+    const int n30 = (cld(rec + 10 + L) - L * L) / P2;
     T a[N1], b[N2], P[NL], Pb[NL];
 #pragma unroll
     for (int m = 0; m < N1; ++m) a[m] = As[(o1 + m) * ST + t];
@@ -779,8 +790,8 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 #pragma unroll
     for (int n3 = 0; n3 < NMAX; ++n3) {
       if (n3 >= n30 && n3 < n_max) {
-        const Coef2<T> c = tb.tc[q0 + n3 - n30];
-        const T d = fma(fp, c.c2, c.c1);
+        const T* tcf = reinterpret_cast<const T*>(tb.tc) + 2 * (q0 + n3 - n30);
+        const T d = fma(fp, cld(tcf + 1), cld(tcf));
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           Pb[m] = fma(d, As[(n3 * P2 + L * L + m) * ST + t], Pb[m]);
@@ -797,17 +808,17 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 #pragma unroll
     for (int m = 0; m < NR; ++m) accR[m] += RUN1 ? ga[m] : gb[m];
 #pragma unroll
-    for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, noth * P2 + LO * LO + m, t, RUN1 ? gb[m] : ga[m], own);
+    for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, noth * P2 + LO * LO + m, t, RUN1 ? gb[m] : ga[m]);
   }
   if (run_n >= 0) {
 #pragma unroll
-    for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m], own);
+    for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m]);
   }
 #pragma unroll
   for (int n = 0; n < NMAX; ++n) {
     if (n < n_max) {
 #pragma unroll
-      for (int m = 0; m < NL; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m], own);
+      for (int m = 0; m < NL; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m]);
     }
   }
 }
@@ -817,10 +828,10 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 // adjoint of block (n2, l) is added to global memory per entry.
 template <class T, int LMAX, int TILE>
 __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                               int nb1, int n_max, int t, bool own, T fp) {
+                                               int nb1, int n_max, int t, T fp) {
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
-  for (int e = 0; e < nb1; ++e) gadd<T, TILE>(Abt, tb.b1_off[e], t, fma(fp, tb.b1_c2[e], tb.b1_c1[e]), own);
+  for (int e = 0; e < nb1; ++e) gadd<T, TILE>(Abt, cld(tb.b1_off + e), t, fma(fp, cld(tb.b1_c2 + e), cld(tb.b1_c1 + e)));
   int base = 0;
   for (int n1 = 0; n1 < n_max; ++n1) {
 #pragma unroll
@@ -830,17 +841,17 @@ __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __re
       for (int m = 0; m < 2 * l + 1; ++m) accR[m] = T(0);
       for (int n2 = n1; n2 < n_max; ++n2) {
         const int e = base + (n2 - n1) * (LMAX + 1) + l;
-        const T d = fma(fp, tb.b2_c2[e], tb.b2_c1[e]);
+        const T d = fma(fp, cld(tb.b2_c2 + e), cld(tb.b2_c1 + e));
         const int o1 = n1 * P2 + l * l, o2 = n2 * P2 + l * l;
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
           const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
           accR[m] = fma(d, x2, accR[m]);
-          gadd<T, TILE>(Abt, o2 + m, t, d * x1, own);
+          gadd<T, TILE>(Abt, o2 + m, t, d * x1);
         }
       }
 #pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m], own);
+      for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m]);
     }
     base += (n_max - n1) * (LMAX + 1);
   }
@@ -859,32 +870,37 @@ __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __re
   X(3, 4, 3) X(4, 0, 4) X(4, 1, 3) X(4, 2, 2) X(4, 2, 4) X(4, 3, 1) X(4, 3, 3) X(4, 4, 0) \
   X(4, 4, 2) X(4, 4, 4)
 
-template <class T, int LMAX, int NMAX, int TILE, int NW, bool COMP>
-__global__ void __launch_bounds__(NW * 64, 2) k_ace_products_units(const T* __restrict__ Ag, T* __restrict__ Abg,
-                                                                int n_act, int na, int n_max, AceTables<T> tb,
-                                                                int nb1, int nb2, T eps,
-                                                                const double* __restrict__ e_anch,
-                                                                const int* __restrict__ active,
-                                                                double* __restrict__ e_site) {
+// Stages the tile's atomic base into LDS, [a][TILE + 1] (atom fastest; the padding
+// column keeps the stride odd).
+template <class T, int TILE>
+__device__ __forceinline__ void stage_tile(const T* __restrict__ Ag, T* As, int q0, int n_act, int na, int nthr) {
   constexpr int ST = TILE + 1;
-  extern __shared__ double smem_raw[];
-  T* As = reinterpret_cast<T*>(smem_raw);
-  T* red = As + (size_t)na * ST;  // [NW][4][TILE]
-  T* fps = red + NW * 4 * TILE;   // [TILE]
-  const int tid = threadIdx.x;
-  const int nthr = NW * 64;
-  const int q0 = blockIdx.x * TILE;
-  for (int e = tid; e < TILE * na; e += nthr) {
+  for (int e = threadIdx.x; e < TILE * na; e += nthr) {
     const int t = e / na, a = e - t * na;
     const int q = q0 + t;
     As[a * ST + t] = q < n_act ? Ag[(size_t)q * na + a] : T(0);
   }
+}
+
+// Energy pass of the float32 product basis: 64 active atoms per block (lane = atom), the
+// label pairs dealt round-robin to the waves, compensated sums of c1.B and c2.B, then
+// E_i = phi1 + F_eps(phi2) (+ anchor) and the embedding slope F_eps'(phi2) for the adjoint.
+template <class T, int LMAX, int NMAX, int TILE, int NW, bool COMP>
+__global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag, int n_act, int na, int n_max,
+                                                        AceTables<T> tb, int nb1, int nb2, T eps,
+                                                        const double* __restrict__ e_anch,
+                                                        const int* __restrict__ active, double* __restrict__ e_site,
+                                                        T* __restrict__ fp_out) {
+  extern __shared__ double smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* red = As + (size_t)na * (TILE + 1);  // [NW][4][TILE]
+  const int tid = threadIdx.x;
+  const int q0 = blockIdx.x * TILE;
+  stage_tile<T, TILE>(Ag, As, q0, n_act, na, NW * 64);
   __syncthreads();
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int t = lane % TILE;
-  const bool own = lane < TILE && q0 + t < n_act;
-  // ------------------------------------------------------------ energy pass
   Acc<T> acc{T(0), T(0), T(0), T(0)};
   if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
   for (int pi = wv; pi < tb.npairs; pi += NW) {
@@ -916,32 +932,52 @@ __global__ void __launch_bounds__(NW * 64, 2) k_ace_products_units(const T* __re
     }
     T dfdx;
     const T f2 = feps<T>(s2 + e2, eps, dfdx);
-    fps[t] = dfdx;
     const int q = q0 + t;
+    fp_out[q] = q < n_act ? dfdx : T(0);
     if (q < n_act) e_site[active[q]] = (double)(s1 + e1) + (double)f2 + e_anch[q];
   }
+}
+
+// Adjoint of the product basis for the units of one launch group G: the tile's atomic
+// base is staged again, the embedding slope is read from the energy pass, and every
+// wave runs its units (see unit_bwd), adding to the tile's adjoint in global memory.
+template <class T, int LMAX, int NMAX, int TILE, int NW, int G>
+__global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict__ Ag, T* __restrict__ Abg,
+                                                            int n_act, int na, int n_max, AceTables<T> tb, int nb1,
+                                                            const T* __restrict__ fp_in) {
+  static_assert(NW == kUnitWaves, "the unit tables are dealt to kUnitWaves waves");
+  extern __shared__ double smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int q0 = blockIdx.x * TILE;
+  stage_tile<T, TILE>(Ag, As, q0, n_act, na, NW * 64);
   __syncthreads();
-  // ----------------------------------------------------------- adjoint units
-  const T fp = fps[t];
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int t = lane % TILE;
+  const T fp = fp_in[q0 + t];
   T* Abt = Abg + (size_t)blockIdx.x * na * TILE;
-  const int ub = __builtin_amdgcn_readfirstlane(tb.wave_units[wv]);
-  const int ue = __builtin_amdgcn_readfirstlane(tb.wave_units[wv + 1]);
+  const int* wu = tb.wave_units;
+  const int* lst = wu + kUnitGroups * (NW + 1);
+  const int ub = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv));
+  const int ue = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv + 1));
   for (int k = ub; k < ue; ++k) {
-    const int u = __builtin_amdgcn_readfirstlane(tb.wave_units[NW + 1 + k]);
+    const int u = cld(lst + k);
     const int* ur = tb.units + u * kUnitRec;
-    const int type = __builtin_amdgcn_readfirstlane(ur[0]);
-    const int L = __builtin_amdgcn_readfirstlane(ur[1]);
-    const int pb = __builtin_amdgcn_readfirstlane(ur[2]);
-    const int pe = __builtin_amdgcn_readfirstlane(ur[3]);
-    const int half = __builtin_amdgcn_readfirstlane(ur[4]);
+    const int type = cld(ur);
+    const int L = cld(ur + 1);
+    const int pb = cld(ur + 2);
+    const int pe = cld(ur + 3);
+    const int half = cld(ur + 4);
     if (L < 0) {
-      low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, t, own, fp);
+      if constexpr (G == 0) low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, t, fp);
       continue;
     }
     const int key = type * (LMAX + 1) + L;
 #define APX_UNIT(A_, B_, C_)                                                                              \
   case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
-    unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, pb, pe, half, n_max, t, own, fp);              \
+    if constexpr (unit_group(C_) == G)                                                                    \
+      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, pb, pe, half, n_max, t, fp);                 \
     break;
     if constexpr (LMAX == 3) {
       switch (key) { APX_UNIT_CASES_3(APX_UNIT) default: break; }
@@ -989,12 +1025,13 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   const int na = m->na;
   const long long n_pad = (long long)((n_act + TILE - 1) / TILE) * TILE;
   const size_t bytes_A = sizeof(T) * (size_t)n_pad * na;
-  APX_ALLOC(ctx, buf, 2 * bytes_A + 2 * sizeof(double) * (size_t)n_act + 256);
+  APX_ALLOC(ctx, buf, 2 * bytes_A + 2 * sizeof(double) * (size_t)n_act + sizeof(T) * (size_t)n_pad + 512);
   AceScratch<T> sc;
   sc.A = buf.as<T>();
   sc.Ab = reinterpret_cast<T*>(reinterpret_cast<char*>(buf.p) + bytes_A);
   sc.e_anch = reinterpret_cast<double*>(reinterpret_cast<char*>(buf.p) + 2 * bytes_A);
   sc.fp_anch = sc.e_anch + n_act;
+  sc.fp = reinterpret_cast<T*>(sc.fp_anch + n_act + 32);
   // float32 without coefficient gradients: unit adjoint with register accumulation
   const bool use_units = sizeof(T) == 4 && dc1 == nullptr;
   sc.tile_size = use_units ? TILE : 0;
@@ -1034,22 +1071,49 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
     }
     const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
-    auto launch = [&](auto kern) -> apx_status {
-      if (ensure_lds(ctx, (const void*)kern, ldsu) != APX_OK) return APX_EDEVICE;
-      ProfScope ps(ctx, "ace.products");
-      kern<<<nblk, NWU * 64, ldsu, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
-                                                  sc.e_anch, active, e_site);
+    const size_t ldse = sizeof(T) * ((size_t)na * (TILE + 1) + NWU * 4 * TILE);
+    const size_t ldsa = sizeof(T) * (size_t)na * (TILE + 1);
+    auto energy = [&](auto kern) -> apx_status {
+      if (ensure_lds(ctx, (const void*)kern, ldse) != APX_OK) return APX_EDEVICE;
+      ProfScope ps(ctx, "ace.energy");
+      kern<<<nblk, NWU * 64, ldse, ctx->stream>>>(sc.A, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
+                                                  sc.e_anch, active, e_site, sc.fp);
       APX_LAUNCH_CHECK(ctx);
       return APX_OK;
     };
+    auto adjoint = [&](auto k0, auto k1, auto k2) -> apx_status {
+      ProfScope ps(ctx, "ace.adjoint");
+      const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2};
+      for (int g = 0; g < kUnitGroups; ++g) {
+        if (m->group_units[g] == 0) continue;
+        if (ensure_lds(ctx, ks[g], ldsa) != APX_OK) return APX_EDEVICE;
+        if (g == 0) k0<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 1) k1<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 2) k2<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        APX_LAUNCH_CHECK(ctx);
+      }
+      return APX_OK;
+    };
     apx_status s;
+#define APX_PRODUCTS(LM_, NM_)                                                                          \
+  s = energy(k_ace_energy<T, LM_, NM_, TILE, NWU, true>);                                               \
+  if (s == APX_OK)                                                                                      \
+    s = adjoint(k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>,     \
+                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>);
     if constexpr (LMAX == 3) {
-      s = m->n_max <= 8 ? launch(k_ace_products_units<T, 3, 8, TILE, NWU, true>)
-                        : launch(k_ace_products_units<T, 3, 12, TILE, NWU, true>);
+      if (m->n_max <= 8) {
+        APX_PRODUCTS(3, 8)
+      } else {
+        APX_PRODUCTS(3, 12)
+      }
     } else {
-      s = m->n_max <= 10 ? launch(k_ace_products_units<T, 4, 10, TILE, NWU, true>)
-                         : launch(k_ace_products_units<T, 4, 12, TILE, NWU, true>);
+      if (m->n_max <= 10) {
+        APX_PRODUCTS(4, 10)
+      } else {
+        APX_PRODUCTS(4, 12)
+      }
     }
+#undef APX_PRODUCTS
     if (s != APX_OK) return s;
   }
   }

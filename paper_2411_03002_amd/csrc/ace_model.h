@@ -13,8 +13,13 @@ constexpr int kAceWaves64 = 8;
 // [4+L] first triple of degree L (L = 0..l_max+1, the last entry closes the list),
 // [10+L] atomic-base offset of the first third block of degree L, [15] n2.
 constexpr int kPairRec = 16;
-// Waves per block of the unit-adjoint product kernel (float32).
+// Waves per block of the unit-adjoint product kernels (float32).
 constexpr int kUnitWaves = 4;
+// The adjoint units are launched in groups by the degree L of their third block
+// (0: L <= 2 and the B1/B2 unit, 1: L = 3, 2: L = 4), one kernel per group, so that each
+// kernel is register-allocated for its own accumulators.
+constexpr int kUnitGroups = 3;
+__host__ __device__ constexpr int unit_group(int L) { return L <= 2 ? 0 : L - 2; }
 // ints per adjoint unit record: type, L (-1: the B1/B2 unit), first pair, end pair,
 // half (0: smaller-degree label n < n_max/2 ... see the kernel), padding.
 constexpr int kUnitRec = 8;
@@ -41,7 +46,7 @@ struct AceTables {
   const T* b2_c2;
   int npairs;
   const int* units;       // [nunits][kUnitRec]
-  const int* wave_units;  // [kUnitWaves + 1 + nunits]: offsets, then unit indices per wave
+  const int* wave_units;  // [kUnitGroups][kUnitWaves + 1] offsets, then unit indices per wave
 };
 
 }  // namespace apx
@@ -52,6 +57,7 @@ struct apx_ace_model {
   long long n_basis = 0;
   int npairs = 0, ntrip = 0, nb1 = 0, nb2 = 0;
   long long coupling_terms = 0, triple_width = 0;  // per-atom work counts
+  int group_units[apx::kUnitGroups] = {0, 0, 0};    // adjoint units per launch group
   double r_cut = 5.0, h = 0.5, s_a = 1.0, eps = 0.1;
   int anchored = 0;
   apx_eam_params anchor{};

@@ -38,6 +38,7 @@ bool coupled(int l1, int l2, int l3) { return ((l1 + l2 + l3) % 2 == 0) && l3 >=
 struct Catalogue {
   long long n_basis = 0;
   std::vector<int> pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units;
+  int group_units[kUnitGroups] = {0, 0, 0};
   int ntrip = 0;
   long long coupling_terms = 0, triple_width = 0;
 };
@@ -162,25 +163,33 @@ Catalogue build_catalogue(int n_max, int l_max) {
     units.push_back({0, -1, 0, 0, 0, 0, 0, 0});
     ucost.push_back(b12 * 3.0 + 30.0 * n_max * LL * LL);
   }
+  // each launch group is dealt to the waves separately, longest processing time first
+  for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());
+  c.wave_units.assign(kUnitGroups * (kUnitWaves + 1), 0);
   std::vector<int> order(units.size());
   for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ucost[a] > ucost[b]; });
-  std::vector<std::vector<int>> per(kUnitWaves);
-  std::vector<double> load(kUnitWaves, 0.0);
-  for (int u : order) {
-    int best = 0;
-    for (int w = 1; w < kUnitWaves; ++w)
-      if (load[w] < load[best]) best = w;
-    per[best].push_back(u);
-    load[best] += ucost[u];
-  }
-  for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());
-  c.wave_units.assign(kUnitWaves + 1, 0);
-  for (int w = 0; w < kUnitWaves; ++w) c.wave_units[w + 1] = c.wave_units[w] + (int)per[w].size();
-  for (int w = 0; w < kUnitWaves; ++w) {
-    // within a wave, keep units of one type together
-    std::sort(per[w].begin(), per[w].end());
-    c.wave_units.insert(c.wave_units.end(), per[w].begin(), per[w].end());
+  for (int g = 0; g < kUnitGroups; ++g) {
+    std::vector<std::vector<int>> per(kUnitWaves);
+    std::vector<double> load(kUnitWaves, 0.0);
+    for (int u : order) {
+      if (unit_group(units[u][1]) != g) continue;
+      int best = 0;
+      for (int w = 1; w < kUnitWaves; ++w)
+        if (load[w] < load[best]) best = w;
+      per[best].push_back(u);
+      load[best] += ucost[u];
+      ++c.group_units[g];
+    }
+    int* off = c.wave_units.data() + g * (kUnitWaves + 1);
+    off[0] = (int)c.wave_units.size() - kUnitGroups * (kUnitWaves + 1);
+    for (int w = 0; w < kUnitWaves; ++w) {
+      // within a wave, keep units of one type together
+      std::sort(per[w].begin(), per[w].end());
+      c.wave_units.insert(c.wave_units.end(), per[w].begin(), per[w].end());
+      off = c.wave_units.data() + g * (kUnitWaves + 1);
+      off[w + 1] = (int)c.wave_units.size() - kUnitGroups * (kUnitWaves + 1);
+    }
   }
   return c;
 }
@@ -275,6 +284,7 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   m->nb1 = (int)c.b1_v.size();
   m->nb2 = (int)c.b2_v.size();
   m->coupling_terms = c.coupling_terms;
+  for (int g = 0; g < kUnitGroups; ++g) m->group_units[g] = c.group_units[g];
   m->triple_width = c.triple_width;
   m->r_cut = d->r_cut;
   m->h = d->h;

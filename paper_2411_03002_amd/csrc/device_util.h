@@ -8,6 +8,17 @@
 namespace apx {
 
 constexpr int kWave = 64;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
+
+// Workgroups are handed to the XCDs round-robin (hardware block b runs on XCD b % 8).
+// Gather kernels read the data of spatial neighbours, so consecutive logical blocks
+// should share an L2: this maps hardware block b to a logical block such that every XCD
+// works through one contiguous range of logical blocks (a bijection on [0, nb)).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
 
 // Minimum image of d = x_j - x_i along one axis of length L (both coordinates in
 // [lo, hi)): d -= L if d >= L/2; d += L if d < -L/2.

@@ -26,29 +26,47 @@ __device__ __forceinline__ void taper(double x, double& p, double& dp) {
   dp = 4.0 * x2 * x * den * den;
 }
 
+// Neighbours are processed in batches of kBatch: the batch's indices and positions are
+// loaded first so that their memory accesses are in flight together, then the pairs are
+// summed in list order (the same order as one at a time).
+constexpr int kBatch = 8;
+
 __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ pos, int n, BoxDev b, EamDev p,
                                                      const int* __restrict__ count, const int* __restrict__ idx,
                                                      int max_nb, const double* __restrict__ w,
                                                      double* __restrict__ e_site, double* __restrict__ rho_out,
                                                      double* __restrict__ ufp, double* __restrict__ u_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
   int cnt = count[i];
   if (cnt > max_nb) cnt = max_nb;
   double rho = 0.0, pair = 0.0;
-  for (int k = 0; k < cnt; ++k) {
-    const int j = idx[(size_t)k * n + i];
-    const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
-    const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
-    const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < p.rc2)) continue;
-    const double r = sqrt(r2);
-    double ps, dps;
-    taper((r - p.rc) * p.inv_h, ps, dps);
-    rho += exp(-p.beta * (r - p.r0)) * ps;
-    pair += exp(-p.alpha * (r - p.r0)) * ps;
+  for (int k0 = 0; k0 < cnt; k0 += kBatch) {
+    int jb[kBatch];
+    double px[kBatch], py[kBatch], pz[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) jb[u] = k0 + u < cnt ? idx[(size_t)(k0 + u) * n + i] : i;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      px[u] = pos[jb[u]];
+      py[u] = pos[(size_t)n + jb[u]];
+      pz[u] = pos[2 * (size_t)n + jb[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const double dx = min_image(px[u] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image(py[u] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image(pz[u] - zi, b.L[2], b.half[2], b.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (k0 + u < cnt && r2 < p.rc2) {
+        const double r = sqrt(r2);
+        double ps, dps;
+        taper((r - p.rc) * p.inv_h, ps, dps);
+        rho += exp(-p.beta * (r - p.r0)) * ps;
+        pair += exp(-p.alpha * (r - p.r0)) * ps;
+      }
+    }
   }
   const double sq = sqrt(rho);
   const double F = rho > 0.0 ? -sq : 0.0;
@@ -64,33 +82,48 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
                                                    const int* __restrict__ count, const int* __restrict__ idx,
                                                    int max_nb, const double* __restrict__ ufp,
                                                    const double* __restrict__ u, double* __restrict__ f) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
   const double ui = u[i], ufi = ufp[i];
   int cnt = count[i];
   if (cnt > max_nb) cnt = max_nb;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int k = 0; k < cnt; ++k) {
-    const int j = idx[(size_t)k * n + i];
-    const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
-    const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
-    const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < p.rc2)) continue;
-    const double r = sqrt(r2);
-    double ps, dps;
-    taper((r - p.rc) * p.inv_h, ps, dps);
-    dps *= p.inv_h;
-    const double eb = exp(-p.beta * (r - p.r0));
-    const double ea = exp(-p.alpha * (r - p.r0));
-    const double drho = eb * (dps - p.beta * ps);
-    const double dphi = p.A * ea * (dps - p.alpha * ps);
-    const double s = 0.5 * (ui + u[j]) * dphi + (ufi + ufp[j]) * drho;
-    const double sr = s / r;
-    fx += sr * dx;
-    fy += sr * dy;
-    fz += sr * dz;
+  for (int k0 = 0; k0 < cnt; k0 += kBatch) {
+    int jb[kBatch];
+    double px[kBatch], py[kBatch], pz[kBatch], uj[kBatch], fj[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) jb[q] = k0 + q < cnt ? idx[(size_t)(k0 + q) * n + i] : i;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      px[q] = pos[jb[q]];
+      py[q] = pos[(size_t)n + jb[q]];
+      pz[q] = pos[2 * (size_t)n + jb[q]];
+      uj[q] = u[jb[q]];
+      fj[q] = ufp[jb[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const double dx = min_image(px[q] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image(py[q] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image(pz[q] - zi, b.L[2], b.half[2], b.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (k0 + q < cnt && r2 < p.rc2) {
+        const double r = sqrt(r2);
+        double ps, dps;
+        taper((r - p.rc) * p.inv_h, ps, dps);
+        dps *= p.inv_h;
+        const double eb = exp(-p.beta * (r - p.r0));
+        const double ea = exp(-p.alpha * (r - p.r0));
+        const double drho = eb * (dps - p.beta * ps);
+        const double dphi = p.A * ea * (dps - p.alpha * ps);
+        const double s = 0.5 * (ui + uj[q]) * dphi + (ufi + fj[q]) * drho;
+        const double sr = s / r;
+        fx += sr * dx;
+        fy += sr * dy;
+        fz += sr * dz;
+      }
+    }
   }
   f[i] = fx;
   f[(size_t)n + i] = fy;

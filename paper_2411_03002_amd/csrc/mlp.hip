@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ pos
                                                   int max_nb, const double* __restrict__ rho,
                                                   const double* __restrict__ csp, const double* __restrict__ f,
                                                   float* __restrict__ feat) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
   int cnt = count[i];

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
                                                       int* __restrict__ idx, int* __restrict__ flags) {
   __shared__ int row[kNbCap][kNbThreads];
   const int t = threadIdx.x;
-  const int i = blockIdx.x * kNbThreads + t;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kNbThreads + t;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
   const double Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];

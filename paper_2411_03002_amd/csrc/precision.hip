@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int
                                              double* __restrict__ csp, double* __restrict__ w0,
                                              double* __restrict__ w) {
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (frozen && frozen[i]) {
     csp[i] = 0.0;

@@ -1,0 +1,192 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The 4,000,000-atom indentation block and the 130,445-atom void run are evaluated by the
+library as the integrator evaluates them (neighbour rows of 80, Hyb1 detection with
+spreading, float64 EAM, float32 ACE on the detected atoms).  The oracle cannot evaluate
+millions of atoms, so sampled atoms are checked one by one on a cluster cut around each
+of them:
+
+* neighbour rows and the centro-symmetry parameter bit for bit (the cluster keeps the
+  sampled atom at the origin, so its displacements are the library's to the last bit);
+* w0 bit for bit, and the spread weight against its definition evaluated over the
+  library's own w0 field;
+* the active list against the mask (every size);
+* site energies and forces against the oracle on the cluster: float64 within 1e-10,
+  float32 ACE within the 10 meV/A budget.
+
+Properties that hold at any size are checked on the whole system: the active list
+against the mask, zero net internal force (frozen atoms included), and NVE energy
+conservation of the void run with frozen weights.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from synth import configs
+from oracle import ace as oace
+from oracle import geometry, hybrid, precision, verlet
+
+from cluster_util import Cutter
+
+pytestmark = pytest.mark.gpu
+
+FTOL = 1e-10        # eV/A, float64 library vs oracle
+BUDGET = 1e-2       # eV/A, float32 ACE vs the float64 oracle
+R_CLUSTER = 10.5    # A: forces on the centre need the densities of neighbours within r_c
+MAX_NB = 80
+
+
+@pytest.fixture(scope="module")
+def ops_ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_03002_amd import ops
+    return ops, ops.Context(0)
+
+
+def _samples(w, frozen, rng, k=6):
+    """Atoms with 0 < w < 1, w = 1, w = 0 (mobile) and frozen atoms."""
+    groups = [np.nonzero((w > 0) & (w < 1))[0], np.nonzero(w == 1)[0]]
+    mob = np.ones(w.shape, bool) if frozen is None else ~frozen.astype(bool)
+    groups.append(np.nonzero((w == 0) & mob)[0])
+    if frozen is not None:
+        groups.append(np.nonzero(frozen.astype(bool))[0])
+    out = []
+    for g in groups:
+        if g.size:
+            out.extend(rng.choice(g, size=min(k, g.size), replace=False).tolist())
+    return np.array(out, dtype=np.int64)
+
+
+def _evaluate(ops, ctx, s, prec, ace_prm, indenter=None):
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 5.5, max_nb=MAX_NB)
+    pr = ops.compute_precision(ctx, atoms, nl, prec)
+    eam = synth.eam_cu_like()
+    model = ops.AceModel(ctx, ace_prm)
+    e = ops.eam_forces(ctx, atoms, nl, eam, pr["w"])
+    a32 = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp32")
+    a64 = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp64")
+    # the integrator's own evaluation at step 0 (same entry points, same launch shapes)
+    md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, skin=0.5, max_nb=MAX_NB, precision_every=10,
+                ace_precision="fp32", mode="adaptive", indenter=indenter)
+    f_md, w_md = md.init(atoms.pos.clone())
+    md.close()
+    return atoms, nl, pr, e, a32, a64, f_md, w_md, model
+
+
+def _check_workload(ops, ctx, s, prec, ace_prm, seed, indenter=None):
+    atoms, nl, pr, e, a32, a64, f_md, w_md, model = _evaluate(ops, ctx, s, prec, ace_prm, indenter)
+    n = s.n
+    w = pr["w"].cpu().numpy()
+    w0 = pr["w0"].cpu().numpy()
+    csp = pr["csp"].cpu().numpy()
+    n_act = int(pr["n_active"])
+    print(f"atoms {n}, detected {n_act} ({n_act / n:.2%})", flush=True)
+    assert 0 < n_act < n
+    # whole-system properties
+    assert np.array_equal(pr["active"].cpu().numpy(), np.nonzero(w > 0)[0])
+    assert np.array_equal(pr["mask"].cpu().numpy(), (w > 0).astype(np.uint8))
+    assert torch.equal(w_md, pr["w"])
+    net = (e["f"] + a64["f"]).sum(dim=1).abs().max().item()
+    assert net < 1e-8, net
+    rng = np.random.default_rng(seed)
+    smp = _samples(w, s.frozen, rng)
+    cut = Cutter(s)
+    cnt = nl.count.cpu().numpy()
+    rows = nl.idx[:, torch.as_tensor(smp, device="cuda")].cpu().numpy()
+    eam_e = e["e_site"].cpu().numpy()
+    f_eam = e["f"].cpu().numpy()
+    f32 = a32["f"].cpu().numpy()
+    f64 = a64["f"].cpu().numpy()
+    e64 = a64["e_site"].cpu().numpy()
+    e32 = a32["e_site"].cpu().numpy()
+    fmd = f_md.cpu().numpy()
+    worst32 = 0.0
+    for k, i in enumerate(smp):
+        cl, idx, c = cut.cluster(i, R_CLUSTER)
+        # neighbour row, bit for bit
+        csr = geometry.neighbor_csr(cl.pos, cl.lo, cl.hi, cl.periodic, 5.5)
+        row = np.sort(idx[csr[1][csr[0][c]:csr[0][c + 1]]])
+        assert cnt[i] == row.size, (i, cnt[i], row.size)
+        assert np.array_equal(rows[:cnt[i], k], row), i
+        # CSP and w0, bit for bit
+        c_ref = precision.csp(cl.pos, cl.lo, cl.hi, cl.periodic, csr, frozen=cl.frozen)[c]
+        assert csp[i] == c_ref or (np.isinf(csp[i]) and np.isinf(c_ref)), (i, csp[i], c_ref)
+        fz = None if s.frozen is None else s.frozen[i:i + 1]
+        w0_ref = precision.w0_from_csp(np.array([c_ref]), prec.csp_lo, prec.csp_hi, prec.switch_kind, fz)[0]
+        assert w0[i] == w0_ref, (i, w0[i], w0_ref)
+        # spread weight from the library's w0 field, by its definition
+        big, bidx, bc = cut.cluster(i, prec.r_hi + 0.5)
+        w_ref = precision.spread(big.pos, big.lo, big.hi, big.periodic, w0[bidx], prec.r_lo, prec.r_hi,
+                                 big.frozen)[bc]
+        assert w[i] == w_ref, (i, w[i], w_ref)
+        # energies and forces on the cluster: only atoms within r_c of the centre keep
+        # their weights (the others cannot change the centre's force)
+        r2 = geometry.sq_dist(cl.pos[0], cl.pos[1], cl.pos[2])
+        wc = np.where(r2 < 25.0, w[idx], 0.0)
+        ev = hybrid.evaluate(cl, synth.eam_cu_like(), ace_prm, wc)
+        assert abs(eam_e[i] - ev["e_eam"][c]) < FTOL, i
+        assert np.max(np.abs(f_eam[:, i] - ev["f_eam"][:, c])) < FTOL, i
+        assert np.max(np.abs(f64[:, i] - ev["f_ace"][:, c])) < FTOL, (i, f64[:, i], ev["f_ace"][:, c])
+        d32 = np.max(np.abs(f32[:, i] - ev["f_ace"][:, c]))
+        worst32 = max(worst32, d32)
+        assert d32 < BUDGET, (i, d32)
+        if w[i] > 0:
+            assert abs(e64[i] - ev["e_ace"][c]) < FTOL, i
+            assert abs(e32[i] - ev["e_ace"][c]) < 1e-3, i
+        # the integrator's total force at step 0 (float32 ACE, indenter included)
+        f_ref = ev["f_eam"][:, c] + ev["f_ace"][:, c]
+        if indenter is not None:
+            fi, _ = verlet.indenter(s.pos[:, i:i + 1], s.lo, s.hi, s.periodic, np.asarray(indenter["center"]),
+                                    indenter["radius"], indenter["k"])
+            f_ref = f_ref + fi[:, 0]
+        assert np.max(np.abs(fmd[:, i] - f_ref)) < BUDGET, i
+    print(f"{smp.size} sampled atoms; float32 ACE force error max {worst32 * 1e3:.5f} meV/A", flush=True)
+
+
+def test_indentation_block_4m_sampled(ops_ctx):
+    ops, ctx = ops_ctx
+    print("\n[case] full size: 100^3-cell indentation block, sampled parity", flush=True)
+    s = configs.cfg2()
+    prm = synth.ace_random(10, 4, oace.num_basis(10, 4), seed=4242, anchored=True)
+    _check_workload(ops, ctx, s, synth.precision_hyb1(), prm, seed=11, indenter=s.meta["indenter"])
+    torch.cuda.empty_cache()
+
+
+def test_void_run_sampled(ops_ctx):
+    ops, ctx = ops_ctx
+    print("\n[case] full size: 32^3-cell void run, sampled parity", flush=True)
+    s = configs.cfg1()
+    prm = synth.ace_random(10, 4, oace.num_basis(10, 4), seed=4242, anchored=True)
+    _check_workload(ops, ctx, s, synth.precision_hyb1(), prm, seed=12)
+
+
+def test_void_run_nve_frozen_weights(ops_ctx):
+    """100 steps of 1 fs with the weights of step 0 kept: the hybrid force is then the
+    exact gradient of a fixed energy, so the total energy is conserved up to the Verlet
+    fluctuation, about 1e-5 eV/atom at this step (a wrong force term drifts by orders of
+    magnitude more)."""
+    ops, ctx = ops_ctx
+    print("\n[case] full size: void run NVE, frozen weights, 100 steps", flush=True)
+    s = configs.cfg1()
+    prm = synth.ace_random(10, 4, oace.num_basis(10, 4), seed=4242, anchored=True)
+    atoms = ops.device_atoms(s)
+    model = ops.AceModel(ctx, prm)
+    md = ops.MD(ctx, atoms, synth.eam_cu_like(), model, synth.precision_hyb1(), dt=1e-3, skin=0.5,
+                max_nb=MAX_NB, precision_every=0, ace_precision="fp32", mode="adaptive")
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(s.vel, device="cuda").contiguous()
+    f, w = md.init(pos)
+    st0 = md.step(pos, vel, f, w, 0)
+    energies = [st0["e_pot"] + st0["e_kin"]]
+    for _ in range(10):
+        st = md.step(pos, vel, f, w, 10)
+        energies.append(st["e_pot"] + st["e_kin"])
+    md.close()
+    drift = (max(energies) - min(energies)) / s.n
+    print(f"detected {st['n_active']}, energy spread {drift:.3e} eV/atom", flush=True)
+    assert st["n_active"] > 0
+    assert drift < 3e-5
