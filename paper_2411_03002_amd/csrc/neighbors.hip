@@ -21,67 +21,70 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
   __shared__ int row[kNbCap][kNbThreads];
   const int t = threadIdx.x;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kNbThreads + t;
-  if (i >= n) return;
-  const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
-  const double Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
-  const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
-  int ci[3];
-  ci[0] = cell_coord(xi, g.lo[0], g.inv_cell[0], g.nc[0]);
-  ci[1] = cell_coord(yi, g.lo[1], g.inv_cell[1], g.nc[1]);
-  ci[2] = cell_coord(zi, g.lo[2], g.inv_cell[2], g.nc[2]);
-  // offsets per axis: -1, 0, +1 when distinct, fewer cells otherwise
-  int olo[3], ohi[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (g.per[d]) {
-      olo[d] = g.nc[d] >= 3 ? -1 : 0;
-      ohi[d] = g.nc[d] >= 3 ? 1 : g.nc[d] - 1;
-    } else {
-      olo[d] = ci[d] > 0 ? -1 : 0;
-      ohi[d] = ci[d] < g.nc[d] - 1 ? 1 : 0;
-    }
-  }
+  const bool valid = i < n;
   int cnt = 0;
-  for (int oz = olo[2]; oz <= ohi[2]; ++oz) {
-    int cz = ci[2] + oz;
-    if (g.per[2]) cz = (cz + g.nc[2]) % g.nc[2];
-    for (int oy = olo[1]; oy <= ohi[1]; ++oy) {
-      int cy = ci[1] + oy;
-      if (g.per[1]) cy = (cy + g.nc[1]) % g.nc[1];
-      for (int ox = olo[0]; ox <= ohi[0]; ++ox) {
-        int cx = ci[0] + ox;
-        if (g.per[0]) cx = (cx + g.nc[0]) % g.nc[0];
-        const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
-        const int b = cell_start[c], e = cell_start[c + 1];
-        for (int a = b; a < e; ++a) {
-          const int j = cell_atoms[a];
-          if (j == i) continue;
-          const double dx = min_image(pos[j] - xi, Lx, hx, g.per[0]);
-          const double dy = min_image(pos[(size_t)n + j] - yi, Ly, hy, g.per[1]);
-          const double dz = min_image(pos[2 * (size_t)n + j] - zi, Lz, hz, g.per[2]);
-          const double r2 = sq_dist_exact(dx, dy, dz);
-          if (r2 < rl2) {
-            if (cnt < kNbCap) {
-              int k = cnt;
-              while (k > 0 && row[k - 1][t] > j) {
-                row[k][t] = row[k - 1][t];
-                --k;
+  if (valid) {
+    const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
+    const double Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    int ci[3];
+    ci[0] = cell_coord(xi, g.lo[0], g.inv_cell[0], g.nc[0]);
+    ci[1] = cell_coord(yi, g.lo[1], g.inv_cell[1], g.nc[1]);
+    ci[2] = cell_coord(zi, g.lo[2], g.inv_cell[2], g.nc[2]);
+    // offsets per axis: -1, 0, +1 when distinct, fewer cells otherwise
+    int olo[3], ohi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (g.per[d]) {
+        olo[d] = g.nc[d] >= 3 ? -1 : 0;
+        ohi[d] = g.nc[d] >= 3 ? 1 : g.nc[d] - 1;
+      } else {
+        olo[d] = ci[d] > 0 ? -1 : 0;
+        ohi[d] = ci[d] < g.nc[d] - 1 ? 1 : 0;
+      }
+    }
+    for (int oz = olo[2]; oz <= ohi[2]; ++oz) {
+      int cz = ci[2] + oz;
+      if (g.per[2]) cz = (cz + g.nc[2]) % g.nc[2];
+      for (int oy = olo[1]; oy <= ohi[1]; ++oy) {
+        int cy = ci[1] + oy;
+        if (g.per[1]) cy = (cy + g.nc[1]) % g.nc[1];
+        for (int ox = olo[0]; ox <= ohi[0]; ++ox) {
+          int cx = ci[0] + ox;
+          if (g.per[0]) cx = (cx + g.nc[0]) % g.nc[0];
+          const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
+          const int b = cell_start[c], e = cell_start[c + 1];
+          for (int a = b; a < e; ++a) {
+            const int j = cell_atoms[a];
+            if (j == i) continue;
+            const double dx = min_image(pos[j] - xi, Lx, hx, g.per[0]);
+            const double dy = min_image(pos[(size_t)n + j] - yi, Ly, hy, g.per[1]);
+            const double dz = min_image(pos[2 * (size_t)n + j] - zi, Lz, hz, g.per[2]);
+            const double r2 = sq_dist_exact(dx, dy, dz);
+            if (r2 < rl2) {
+              if (cnt < kNbCap) {
+                int k = cnt;
+                while (k > 0 && row[k - 1][t] > j) {
+                  row[k][t] = row[k - 1][t];
+                  --k;
+                }
+                row[k][t] = j;
               }
-              row[k][t] = j;
+              ++cnt;
             }
-            ++cnt;
           }
         }
       }
     }
   }
-  count[i] = cnt;
-  if (cnt > max_nb) {
-    atomicOr(&flags[0], 4);
-    atomicMax(&flags[1], cnt);
-  } else {
-    atomicMax(&flags[1], cnt);
+  // the longest row and the capacity flag: one atomic per wave (the block is one wave)
+  const int longest = wave_max(cnt);
+  if (t == 0) {
+    if (longest > max_nb) atomicOr(&flags[0], 4);
+    atomicMax(&flags[1], longest);
   }
+  if (!valid) return;
+  count[i] = cnt;
   const int m = cnt < max_nb ? cnt : max_nb;
   for (int k = 0; k < m; ++k) idx[(size_t)k * n + i] = row[k][t];
 }
