@@ -823,37 +823,35 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   }
 }
 
-// B1 and B2 adjoint.  B2 entries are stored in catalogue order (n1, n2 >= n1, l); for
-// each (n1, l) the adjoint of block (n1, l) is accumulated over n2 in registers, the
-// adjoint of block (n2, l) is added to global memory per entry.
+// B1 and B2 adjoint of one first label n1: its B1 entry (entry n1) and its B2 entries,
+// stored in catalogue order (n1, n2 >= n1, l).  For each l the adjoint of block (n1, l) is
+// accumulated over n2 in registers, the adjoint of block (n2, l) is added per entry.
 template <class T, int LMAX, int TILE>
 __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                               int nb1, int n_max, int t, T fp) {
+                                               int nb1, int n_max, int n1, int t, T fp) {
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
-  for (int e = 0; e < nb1; ++e) gadd<T, TILE>(Abt, cld(tb.b1_off + e), t, fma(fp, cld(tb.b1_c2 + e), cld(tb.b1_c1 + e)));
-  int base = 0;
-  for (int n1 = 0; n1 < n_max; ++n1) {
+  if (n1 < nb1) gadd<T, TILE>(Abt, cld(tb.b1_off + n1), t, fma(fp, cld(tb.b1_c2 + n1), cld(tb.b1_c1 + n1)));
+  // entries of the labels before n1: sum over n' < n1 of (n_max - n')(l_max + 1)
+  const int base = (LMAX + 1) * (n1 * n_max - n1 * (n1 - 1) / 2);
 #pragma unroll
-    for (int l = 0; l <= LMAX; ++l) {
-      T accR[2 * l + 1];
+  for (int l = 0; l <= LMAX; ++l) {
+    T accR[2 * l + 1];
 #pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) accR[m] = T(0);
-      for (int n2 = n1; n2 < n_max; ++n2) {
-        const int e = base + (n2 - n1) * (LMAX + 1) + l;
-        const T d = fma(fp, cld(tb.b2_c2 + e), cld(tb.b2_c1 + e));
-        const int o1 = n1 * P2 + l * l, o2 = n2 * P2 + l * l;
+    for (int m = 0; m < 2 * l + 1; ++m) accR[m] = T(0);
+    for (int n2 = n1; n2 < n_max; ++n2) {
+      const int e = base + (n2 - n1) * (LMAX + 1) + l;
+      const T d = fma(fp, cld(tb.b2_c2 + e), cld(tb.b2_c1 + e));
+      const int o1 = n1 * P2 + l * l, o2 = n2 * P2 + l * l;
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) {
-          const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
-          accR[m] = fma(d, x2, accR[m]);
-          gadd<T, TILE>(Abt, o2 + m, t, d * x1);
-        }
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
+        accR[m] = fma(d, x2, accR[m]);
+        gadd<T, TILE>(Abt, o2 + m, t, d * x1);
       }
-#pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m]);
     }
-    base += (n_max - n1) * (LMAX + 1);
+#pragma unroll
+    for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m]);
   }
 }
 
@@ -970,7 +968,7 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
     const int pe = cld(ur + 3);
     const int half = cld(ur + 4);
     if (L < 0) {
-      if constexpr (G == 0) low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, t, fp);
+      if constexpr (G == 0) low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, pb, t, fp);
       continue;
     }
     const int key = type * (LMAX + 1) + L;

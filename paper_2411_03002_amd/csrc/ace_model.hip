@@ -126,11 +126,8 @@ Catalogue build_catalogue(int n_max, int l_max) {
     cost.push_back(pt.cost);
   }
   c.ntrip = base;
-  // cost of the B1/B2 part
-  double b12 = (double)n_max;
-  for (size_t q = 0; q < c.b2_v.size(); ++q) b12 += 2 * c.b2_off[3 * q + 2] + 1 + 2;
-  // adjoint units (type, L) over the contiguous pair range of each type, plus one unit for
-  // B1/B2, dealt to the waves by longest processing time first
+  // adjoint units (type, L) over the contiguous pair range of each type, plus the B1/B2
+  // units, dealt to the waves by longest processing time first
   std::vector<std::array<int, kUnitRec>> units;
   const int half_n = (n_max + 1) / 2;
   std::vector<double> ucost;
@@ -160,8 +157,13 @@ Catalogue build_catalogue(int n_max, int l_max) {
       }
       q = e;
     }
-    units.push_back({0, -1, 0, 0, 0, 0, 0, 0});
-    ucost.push_back(b12 * 3.0 + 30.0 * n_max * LL * LL);
+    // B1/B2: one unit per first label n1 (its B1 entry and its B2 entries n2 >= n1)
+    for (int n1 = 0; n1 < n_max; ++n1) {
+      double cst = 3.0;
+      for (int l = 0; l < LL; ++l) cst += (n_max - n1) * (2 * l + 1) * 6.0 + (2 * l + 1) * 3.0;
+      units.push_back({0, -1, n1, 0, 0, 0, 0, 0});
+      ucost.push_back(cst);
+    }
   }
   // each launch group is dealt to the waves separately, longest processing time first
   for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());

@@ -9,6 +9,7 @@ namespace apx {
 
 constexpr int kNbThreads = 64;  // one wave per block: each thread owns one row in LDS
 constexpr int kNbCap = 128;     // row capacity held in LDS
+constexpr int kBatch = 8;       // candidates whose loads are issued together
 
 // One thread per atom.  Candidate atoms come from the 27 (or fewer, for grids with fewer
 // than 3 cells along a periodic axis) neighbouring cells; accepted indices are kept
@@ -54,23 +55,37 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
           if (g.per[0]) cx = (cx + g.nc[0]) % g.nc[0];
           const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
           const int b = cell_start[c], e = cell_start[c + 1];
-          for (int a = b; a < e; ++a) {
-            const int j = cell_atoms[a];
-            if (j == i) continue;
-            const double dx = min_image(pos[j] - xi, Lx, hx, g.per[0]);
-            const double dy = min_image(pos[(size_t)n + j] - yi, Ly, hy, g.per[1]);
-            const double dz = min_image(pos[2 * (size_t)n + j] - zi, Lz, hz, g.per[2]);
-            const double r2 = sq_dist_exact(dx, dy, dz);
-            if (r2 < rl2) {
-              if (cnt < kNbCap) {
-                int k = cnt;
-                while (k > 0 && row[k - 1][t] > j) {
-                  row[k][t] = row[k - 1][t];
-                  --k;
+          // candidates in batches: the batch's indices and positions are loaded first so
+          // that their memory accesses are in flight together
+          for (int a0 = b; a0 < e; a0 += kBatch) {
+            int jb[kBatch];
+            double px[kBatch], py[kBatch], pz[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) jb[q] = a0 + q < e ? cell_atoms[a0 + q] : i;
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+              px[q] = pos[jb[q]];
+              py[q] = pos[(size_t)n + jb[q]];
+              pz[q] = pos[2 * (size_t)n + jb[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+              const int j = jb[q];
+              const double dx = min_image(px[q] - xi, Lx, hx, g.per[0]);
+              const double dy = min_image(py[q] - yi, Ly, hy, g.per[1]);
+              const double dz = min_image(pz[q] - zi, Lz, hz, g.per[2]);
+              const double r2 = sq_dist_exact(dx, dy, dz);
+              if (j != i && r2 < rl2) {
+                if (cnt < kNbCap) {
+                  int k = cnt;
+                  while (k > 0 && row[k - 1][t] > j) {
+                    row[k][t] = row[k - 1][t];
+                    --k;
+                  }
+                  row[k][t] = j;
                 }
-                row[k][t] = j;
+                ++cnt;
               }
-              ++cnt;
             }
           }
         }

@@ -22,9 +22,15 @@ __device__ __forceinline__ double switch_w0(double c, const PrecDev& p) {
   return 1.0 - fcut_exact(x);
 }
 
+constexpr int kBatch = 8;  // neighbours whose loads are issued together
+
 // One thread per atom.  Keeps the M nearest candidates within r_cut sorted by
 // (squared distance, index): the row is in ascending index, so a strict comparison
-// keeps the smaller index first among equal distances.
+// keeps the smaller index first among equal distances.  The sorted slots carry the
+// squared distance and the row position only; the M displacements are recomputed
+// (identically) for the pair stage.  EXACT: M and HALF are the parameters' N + N_buffer
+// and N/2; otherwise they are upper bounds and p.m, p.half apply.
+template <int M, int HALF, bool EXACT>
 __global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int n, Grid g,
                                              const uint8_t* __restrict__ frozen,
                                              const int* __restrict__ count, const int* __restrict__ idx,
@@ -42,61 +48,85 @@ __global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int
   }
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
   const double hx = 0.5 * g.L[0], hy = 0.5 * g.L[1], hz = 0.5 * g.L[2];
-  double kr[kMaxM], kx[kMaxM], ky[kMaxM], kz[kMaxM];
+  const int m = EXACT ? M : p.m;
+  double kr[M];
+  int ks[M];
 #pragma unroll
-  for (int a = 0; a < kMaxM; ++a) {
+  for (int a = 0; a < M; ++a) {
     kr[a] = INFINITY;
-    kx[a] = ky[a] = kz[a] = 0.0;
+    ks[a] = 0;
   }
   int found = 0;
   int cnt = count[i];
   if (cnt > max_nb) cnt = max_nb;
-  for (int k = 0; k < cnt; ++k) {
-    const int j = idx[(size_t)k * n + i];
-    const double dx = min_image(pos[j] - xi, g.L[0], hx, g.per[0]);
-    const double dy = min_image(pos[(size_t)n + j] - yi, g.L[1], hy, g.per[1]);
-    const double dz = min_image(pos[2 * (size_t)n + j] - zi, g.L[2], hz, g.per[2]);
-    const double r2 = sq_dist_exact(dx, dy, dz);
-    if (!(r2 < p.rc2)) continue;
-    ++found;
-    if (!(r2 < kr[kMaxM - 1])) continue;
-    // insertion into the sorted arrays, unrolled so the arrays stay in registers
-    // once the new entry has been placed every later slot shifts by one, which keeps
-    // equal distances in arrival (ascending index) order
-    double cr = r2, cx = dx, cy = dy, cz = dz;
-    bool shifting = false;
+  for (int k0 = 0; k0 < cnt; k0 += kBatch) {
+    int jb[kBatch];
+    double px[kBatch], py[kBatch], pz[kBatch];
 #pragma unroll
-    for (int a = 0; a < kMaxM; ++a) {
-      const bool take = shifting || cr < kr[a];
-      shifting = take;
-      const double tr = kr[a], tx = kx[a], ty = ky[a], tz = kz[a];
-      kr[a] = take ? cr : tr;
-      kx[a] = take ? cx : tx;
-      ky[a] = take ? cy : ty;
-      kz[a] = take ? cz : tz;
-      cr = take ? tr : cr;
-      cx = take ? tx : cx;
-      cy = take ? ty : cy;
-      cz = take ? tz : cz;
+    for (int q = 0; q < kBatch; ++q) jb[q] = k0 + q < cnt ? idx[(size_t)(k0 + q) * n + i] : i;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      px[q] = pos[jb[q]];
+      py[q] = pos[(size_t)n + jb[q]];
+      pz[q] = pos[2 * (size_t)n + jb[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const double dx = min_image(px[q] - xi, g.L[0], hx, g.per[0]);
+      const double dy = min_image(py[q] - yi, g.L[1], hy, g.per[1]);
+      const double dz = min_image(pz[q] - zi, g.L[2], hz, g.per[2]);
+      const double r2 = sq_dist_exact(dx, dy, dz);
+      if (!(k0 + q < cnt && r2 < p.rc2)) continue;
+      ++found;
+      if (!(r2 < kr[M - 1])) continue;
+      // insertion into the sorted slots, unrolled so they stay in registers; once the new
+      // entry has been placed every later slot shifts by one, which keeps equal distances
+      // in arrival (ascending index) order
+      double cr = r2;
+      int cs = k0 + q;
+      bool shifting = false;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const bool take = shifting || cr < kr[a];
+        shifting = take;
+        const double tr = kr[a];
+        const int ts = ks[a];
+        kr[a] = take ? cr : tr;
+        ks[a] = take ? cs : ts;
+        cr = take ? tr : cr;
+        cs = take ? ts : cs;
+      }
     }
   }
   double c;
-  if (found < p.m) {
+  if (found < m) {
     c = INFINITY;
   } else {
-    double best[kMaxHalf];
+    double kx[M], ky[M], kz[M];
 #pragma unroll
-    for (int a = 0; a < kMaxHalf; ++a) best[a] = INFINITY;
+    for (int a = 0; a < M; ++a) {
+      if (a < m) {
+        const int j = idx[(size_t)ks[a] * n + i];
+        kx[a] = min_image(pos[j] - xi, g.L[0], hx, g.per[0]);
+        ky[a] = min_image(pos[(size_t)n + j] - yi, g.L[1], hy, g.per[1]);
+        kz[a] = min_image(pos[2 * (size_t)n + j] - zi, g.L[2], hz, g.per[2]);
+      } else {
+        kx[a] = ky[a] = kz[a] = 0.0;
+      }
+    }
+    double best[HALF];
 #pragma unroll
-    for (int a = 0; a < kMaxM; ++a) {
+    for (int a = 0; a < HALF; ++a) best[a] = INFINITY;
 #pragma unroll
-      for (int b = a + 1; b < kMaxM; ++b) {
-        if (b < p.m) {
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+      for (int b = a + 1; b < M; ++b) {
+        if (EXACT || b < m) {
           const double sx = kx[a] + kx[b], sy = ky[a] + ky[b], sz = kz[a] + kz[b];
           double v = sq_dist_exact(sx, sy, sz);
           bool shifting = false;
 #pragma unroll
-          for (int q = 0; q < kMaxHalf; ++q) {
+          for (int q = 0; q < HALF; ++q) {
             const bool take = shifting || v < best[q];
             shifting = take;
             const double t = best[q];
@@ -108,8 +138,8 @@ __global__ void __launch_bounds__(256) k_csp(const double* __restrict__ pos, int
     }
     c = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxHalf; ++q)
-      if (q < p.half) c = c + best[q];
+    for (int q = 0; q < HALF; ++q)
+      if (EXACT || q < p.half) c = c + best[q];
   }
   csp[i] = c;
   double v0 = switch_w0(c, p);
@@ -268,8 +298,12 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   pd.rc2 = p->r_cut * p->r_cut;
   if (!(p->flags & APX_PREC_CSP_GIVEN)) {
   ProfScope ps(ctx, "prec.csp");
-  k_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, g, atoms->frozen, nl->count, nl->idx,
-                                                     nl->max_nb, pd, w0_extra, csp, w0, w);
+  if (pd.m == 12 && pd.half == 6)
+    k_csp<12, 6, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, w);
+  else
+    k_csp<kMaxM, kMaxHalf, false><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, w);
   APX_LAUNCH_CHECK(ctx);
   } else {
     ProfScope ps(ctx, "prec.switch");
