@@ -253,6 +253,19 @@ __device__ __forceinline__ void acc_add(T& s, T& e, T c, T B) {
   }
 }
 
+// Adds x to the compensated sum (s, e): TwoSum, the rounding error kept in e.
+template <class T, bool COMP>
+__device__ __forceinline__ void acc_sum(T& s, T& e, T x) {
+  if constexpr (COMP) {
+    const T sn = s + x;
+    const T bp = sn - s;
+    e += (s - (sn - bp)) + (x - bp);
+    s = sn;
+  } else {
+    s += x;
+  }
+}
+
 template <class T, int TILE>
 __device__ __forceinline__ void lds_add(T* p, T v, bool on) {
   if (on) atomicAdd(p, v);
@@ -293,7 +306,9 @@ __device__ __forceinline__ void pair_fwd(const T* __restrict__ As, const int* re
 }
 
 // Energy contribution of one label pair with the third-block loop unrolled over the
-// radial index (coefficient loads of a segment issued together).
+// radial index (coefficient loads of a segment issued together).  The pair's terms c.B
+// (at most (l_max + 1) n_max of them) are summed by fused multiply-adds, and the pair's
+// two partial sums enter the running sums with compensation.
 template <class T, int LMAX, int NMAX, int TILE, bool COMP, int L1, int L2>
 __device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
                                            int n_max, Acc<T>& acc) {
@@ -309,6 +324,7 @@ __device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* 
 #pragma unroll
   for (int m = 0; m < P2; ++m) P[m] = T(0);
   C::template fwd<T>(a, bb, P);
+  T p1 = T(0), p2 = T(0);
 #pragma unroll
   for (int L = 0; L <= LMAX; ++L) {
     if ((C::kMask >> L) & 1) {
@@ -323,13 +339,15 @@ __device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* 
             T B = T(0);
 #pragma unroll
             for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[L * L + mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
-            acc_add<T, COMP>(acc.s1, acc.e1, c.c1, B);
-            acc_add<T, COMP>(acc.s2, acc.e2, c.c2, B);
+            p1 = fma(c.c1, B, p1);
+            p2 = fma(c.c2, B, p2);
           }
         }
       }
     }
   }
+  acc_sum<T, COMP>(acc.s1, acc.e1, p1);
+  acc_sum<T, COMP>(acc.s2, acc.e2, p2);
 }
 
 template <class T, int LMAX, int TILE, bool DC, int L1, int L2>
@@ -711,8 +729,10 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
 //   acc3[n3][M]  the adjoint of every third block (n3, L)            (registers)
 //   accR[m]      the adjoint of the pair label with the larger degree, accumulated over
 //                the run of pairs sharing it (pairs are sorted by it)
+//   accO[h][m]   the adjoint of the other pair label (one of at most (NMAX + 1)/2 values
+//                in the unit's half)
 // and adds them to the tile's adjoint in global memory with float atomics when a run or
-// the unit ends; the adjoint of the other pair label is added per pair.
+// the unit ends.
 // Every lane adds, padded lanes (beyond the last active atom) included: their slots lie
 // inside the tile's region and are never read back.
 template <class T, int TILE>
@@ -744,14 +764,20 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   const int hn = (n_max + 1) / 2;
   const int obase = half ? hn : 0;
   const int oend = half ? n_max : hn;
+  constexpr int NH = (NMAX + 1) / 2;  // labels in a half, at most
   T acc3[NMAX][NL];
   T accR[NR];
+  T accO[NH][NO];  // adjoint of the other label, by its position in the half
 #pragma unroll
   for (int n = 0; n < NMAX; ++n) {
 #pragma unroll
     for (int m = 0; m < NL; ++m) acc3[n][m] = T(0);
   }
-
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+#pragma unroll
+    for (int m = 0; m < NO; ++m) accO[h][m] = T(0);
+  }
 #pragma unroll
   for (int m = 0; m < NR; ++m) accR[m] = T(0);
   int run_n = -1;
@@ -807,12 +833,26 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
     C::template bwd<T>(a, b, Pb, ga, gb);
 #pragma unroll
     for (int m = 0; m < NR; ++m) accR[m] += RUN1 ? ga[m] : gb[m];
+    // the other label is wave-uniform: a scalar branch picks its accumulator
+    const int oh = noth - obase;
 #pragma unroll
-    for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, noth * P2 + LO * LO + m, t, RUN1 ? gb[m] : ga[m]);
+    for (int h = 0; h < NH; ++h) {
+      if (h == oh) {
+#pragma unroll
+        for (int m = 0; m < NO; ++m) accO[h][m] += RUN1 ? gb[m] : ga[m];
+      }
+    }
   }
   if (run_n >= 0) {
 #pragma unroll
     for (int m = 0; m < NR; ++m) gadd<T, TILE>(Abt, run_n * P2 + LR * LR + m, t, accR[m]);
+  }
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    if (obase + h < oend) {
+#pragma unroll
+      for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, (obase + h) * P2 + LO * LO + m, t, accO[h][m]);
+    }
   }
 #pragma unroll
   for (int n = 0; n < NMAX; ++n) {
