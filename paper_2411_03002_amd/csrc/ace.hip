@@ -766,12 +766,16 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   const int oend = half ? n_max : hn;
   constexpr int NH = (NMAX + 1) / 2;  // labels in a half, at most
   T acc3[NMAX][NL];
+  T A3[NMAX][NL];  // the unit's third blocks, read once for all its pairs
   T accR[NR];
   T accO[NH][NO];  // adjoint of the other label, by its position in the half
 #pragma unroll
   for (int n = 0; n < NMAX; ++n) {
 #pragma unroll
-    for (int m = 0; m < NL; ++m) acc3[n][m] = T(0);
+    for (int m = 0; m < NL; ++m) {
+      acc3[n][m] = T(0);
+      A3[n][m] = n < n_max ? As[(n * P2 + L * L + m) * ST + t] : T(0);
+    }
   }
 #pragma unroll
   for (int h = 0; h < NH; ++h) {
@@ -820,7 +824,7 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
         const T d = fma(fp, cld(tcf + 1), cld(tcf));
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
-          Pb[m] = fma(d, As[(n3 * P2 + L * L + m) * ST + t], Pb[m]);
+          Pb[m] = fma(d, A3[n3][m], Pb[m]);
           acc3[n3][m] = fma(d, P[m], acc3[n3][m]);
         }
       }
