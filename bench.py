@@ -132,7 +132,9 @@ def cpu_baseline(sample_cells=(8, 8, 100), budget_s=30.0):
 
 def run_learned(args):
     """Learned precision indicator: 200 method-generated 16,384-atom snapshots (bulk, 1 %
-    vacancies, 8 A void, (100) slab at 300-1200 K; 180 train / 20 validation), 20 epochs of
+    vacancies, 8 A void, (100) slab, thermalised at 300-1200 K by 500 steps of the fast
+    potential from Maxwell velocities at twice the temperature; 180 train / 20
+    validation), 20 epochs of
     Adam (batch 4096, lr 1e-3) with the library's kernels, then the 130,445-atom void run
     (100 steps, weights every 10) with the centro-symmetry criterion and with the learned
     criterion: atom-steps/s of each, and misassigned atoms and force errors of both
@@ -150,7 +152,9 @@ def run_learned(args):
     t0 = time.perf_counter()
     feats, labels = [], []
     for k in range(200):
-        snap = learned.snapshot(ctx, configs.cfg4_snapshot(k), eam, model, prec, "fp32")
+        start = configs.cfg4_snapshot(k)
+        atoms_k = learned.thermalize(ctx, start, eam, start.meta["md_steps"])
+        snap = learned.snapshot(ctx, atoms_k, eam, model, prec, "fp32")
         feats.append(snap.feat)
         labels.append(snap.label)
     torch.cuda.synchronize()

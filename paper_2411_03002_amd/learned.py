@@ -45,9 +45,23 @@ class Snapshot:
     csp: torch.Tensor    # [n] float64
 
 
-def snapshot(ctx: ops.Context, system, eam, ace: ops.AceModel, prec, precision: str = "fp32") -> Snapshot:
-    """Features and labels of one configuration (all atoms)."""
+def thermalize(ctx: ops.Context, system, eam, steps: int) -> ops.DeviceAtoms:
+    """Integrates ``system`` (positions and velocities) with the fast potential for
+    ``steps`` steps of 1 fs and returns the final positions on the device."""
     atoms = ops.device_atoms(system)
+    md = ops.MD(ctx, atoms, eam, None, None, dt=1e-3, mode="eam", precision_every=0)
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(system.vel, dtype=torch.float64, device=pos.device).contiguous()
+    f, w = md.init(pos)
+    md.step(pos, vel, f, w, steps)
+    md.close()
+    return ops.DeviceAtoms(pos, atoms.lo, atoms.hi, atoms.periodic, atoms.frozen)
+
+
+def snapshot(ctx: ops.Context, system, eam, ace: ops.AceModel, prec, precision: str = "fp32") -> Snapshot:
+    """Features and labels of one configuration (all atoms); ``system`` is a synthetic
+    system or atoms already on the device."""
+    atoms = system if isinstance(system, ops.DeviceAtoms) else ops.device_atoms(system)
     nl = ops.build_neighbors(ctx, atoms, 5.5)
     e = ops.eam_forces(ctx, atoms, nl, eam, None)
     pr = ops.compute_precision(ctx, atoms, nl, dataclasses.replace(prec, r_hi=0.0) if dataclasses.is_dataclass(prec) else prec)

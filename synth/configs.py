@@ -135,16 +135,23 @@ def cfg3(kind: str, seed: int = SEED0 + 3, cells: int = 16) -> System:
 
 
 def cfg4_snapshot(index: int, seed: int = SEED0 + 4, cells: int = 16) -> System:
-    """Training snapshot ``index`` (0..199): structure family = index % 4 (bulk,
-    1 % vacancies, 8 A void, (100) slab), temperature = {300, 600, 900, 1200}[(index//4) % 4]."""
+    """Starting state of training snapshot ``index`` (0..199): structure family =
+    index % 4 (bulk, 1 % vacancies, 8 A void, (100) slab), target temperature
+    T = {300, 600, 900, 1200}[(index // 4) % 4].  Atoms sit on their lattice sites with
+    Maxwell velocities at 2T; integrating it with the fast potential (``meta['md_steps']``
+    steps of 1 fs) brings it to about T by equipartition."""
     fam = index % 4
     T = [300.0, 600.0, 900.0, 1200.0][(index // 4) % 4]
     sd = seed * 1000 + index
     if fam == 0:
-        return bulk(cells, sd, temperature=T)
-    if fam == 1:
-        return bulk(cells, sd, temperature=T, vacancies=int(round(0.01 * 4 * cells ** 3)))
-    if fam == 2:
-        return bulk(cells, sd, temperature=T, void_radius=8.0)
-    return slab100(cells, cells, cells, sd, temperature=T, frozen_planes=0,
-                   sigma=thermal_sigma(T), velocities=False)
+        s = bulk(cells, sd, temperature=2 * T, velocities=True, sigma=0.0)
+    elif fam == 1:
+        s = bulk(cells, sd, temperature=2 * T, vacancies=int(round(0.01 * 4 * cells ** 3)), velocities=True,
+                 sigma=0.0)
+    elif fam == 2:
+        s = bulk(cells, sd, temperature=2 * T, void_radius=8.0, velocities=True, sigma=0.0)
+    else:
+        s = slab100(cells, cells, cells, sd, temperature=2 * T, frozen_planes=0, sigma=0.0, velocities=True)
+    s.meta["temperature"] = T
+    s.meta["md_steps"] = 500
+    return s
