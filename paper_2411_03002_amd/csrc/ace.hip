@@ -750,7 +750,7 @@ __device__ __forceinline__ X cld(const X* p) {
 
 template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
 __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                         int pb, int pe, int half, int n_max, int t, T fp) {
+                                         int eb, int ee, int half, int n_max, int t, T fp) {
   using C = Couple3<LMAX, L1, L2, L>;
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
@@ -760,6 +760,7 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   constexpr int NO = RUN1 ? N2 : N1;
   constexpr int LR = RUN1 ? L1 : L2;
   constexpr int LO = RUN1 ? L2 : L1;
+  static_assert(NMAX <= kAdjC2 - kAdjC1, "the pair stream holds coefficients for n3 < 12");
   // this unit covers the pairs whose smaller-degree label lies in one half of [0, n_max)
   const int hn = (n_max + 1) / 2;
   const int obase = half ? hn : 0;
@@ -785,16 +786,11 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 #pragma unroll
   for (int m = 0; m < NR; ++m) accR[m] = T(0);
   int run_n = -1;
-  for (int pi = pb; pi < pe; ++pi) {
-    const int* rec = tb.pairs + pi * kPairRec;
-    const int q0 = cld(rec + 4 + L);
-    const int q1 = cld(rec + 5 + L);
-    if (q0 == q1) continue;
-    const int n1 = cld(rec + 3);
-    const int n2 = cld(rec + 15);
-    const int nrun = RUN1 ? n1 : n2;
-    const int noth = RUN1 ? n2 : n1;
-    if (noth < obase || noth >= oend) continue;
+  for (int e = eb; e < ee; ++e) {
+    const int* E = tb.adj_i + (size_t)e * kAdjRec;
+    const T* Ec = reinterpret_cast<const T*>(tb.adj_f) + (size_t)e * kAdjRec;
+    const int nrun = cld(E + 2);
+    const int noth = cld(E + 3);
     if (nrun != run_n) {
       if (run_n >= 0) {
 #pragma unroll
@@ -804,8 +800,8 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
       for (int m = 0; m < NR; ++m) accR[m] = T(0);
       run_n = nrun;
     }
-    const int o1 = cld(rec), o2 = cld(rec + 1);
-    const int n30 = (cld(rec + 10 + L) - L * L) / P2;
+    const int o1 = cld(E), o2 = cld(E + 1);
+    const int n30 = cld(E + 4);
     T a[N1], b[N2], P[NL], Pb[NL];
 #pragma unroll
     for (int m = 0; m < N1; ++m) a[m] = As[(o1 + m) * ST + t];
@@ -820,8 +816,7 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 #pragma unroll
     for (int n3 = 0; n3 < NMAX; ++n3) {
       if (n3 >= n30 && n3 < n_max) {
-        const T* tcf = reinterpret_cast<const T*>(tb.tc) + 2 * (q0 + n3 - n30);
-        const T d = fma(fp, cld(tcf + 1), cld(tcf));
+        const T d = fma(fp, cld(Ec + kAdjC2 + n3), cld(Ec + kAdjC1 + n3));
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           Pb[m] = fma(d, A3[n3][m], Pb[m]);
@@ -1009,8 +1004,9 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
     const int type = cld(ur);
     const int L = cld(ur + 1);
     const int pb = cld(ur + 2);
-    const int pe = cld(ur + 3);
     const int half = cld(ur + 4);
+    const int eb = cld(ur + 5);
+    const int ee = cld(ur + 6);
     if (L < 0) {
       if constexpr (G == 0) low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, pb, t, fp);
       continue;
@@ -1019,7 +1015,7 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
 #define APX_UNIT(A_, B_, C_)                                                                              \
   case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
     if constexpr (unit_group(C_) == G)                                                                    \
-      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, pb, pe, half, n_max, t, fp);                 \
+      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp);                 \
     break;
     if constexpr (LMAX == 3) {
       switch (key) { APX_UNIT_CASES_3(APX_UNIT) default: break; }
@@ -1123,15 +1119,17 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
       return APX_OK;
     };
-    auto adjoint = [&](auto k0, auto k1, auto k2) -> apx_status {
+    auto adjoint = [&](auto k0, auto k1, auto k2, auto k3) -> apx_status {
       ProfScope ps(ctx, "ace.adjoint");
-      const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2};
+      static_assert(kUnitGroups == 4, "one kernel per launch group");
+      const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2, (const void*)k3};
       for (int g = 0; g < kUnitGroups; ++g) {
         if (m->group_units[g] == 0) continue;
         if (ensure_lds(ctx, ks[g], ldsa) != APX_OK) return APX_EDEVICE;
         if (g == 0) k0<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         if (g == 1) k1<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         if (g == 2) k2<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 3) k3<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         APX_LAUNCH_CHECK(ctx);
       }
       return APX_OK;
@@ -1141,7 +1139,7 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   s = energy(k_ace_energy<T, LM_, NM_, TILE, NWU, true>);                                               \
   if (s == APX_OK)                                                                                      \
     s = adjoint(k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>,     \
-                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>);
+                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 3>);
     if constexpr (LMAX == 3) {
       if (m->n_max <= 8) {
         APX_PRODUCTS(3, 8)

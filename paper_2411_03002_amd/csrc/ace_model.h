@@ -16,13 +16,21 @@ constexpr int kPairRec = 16;
 // Waves per block of the unit-adjoint product kernels (float32).
 constexpr int kUnitWaves = 4;
 // The adjoint units are launched in groups by the degree L of their third block
-// (0: L <= 2 and the B1/B2 unit, 1: L = 3, 2: L = 4), one kernel per group, so that each
-// kernel is register-allocated for its own accumulators.
-constexpr int kUnitGroups = 3;
-__host__ __device__ constexpr int unit_group(int L) { return L <= 2 ? 0 : L - 2; }
-// ints per adjoint unit record: type, L (-1: the B1/B2 unit), first pair, end pair,
-// half (0: smaller-degree label n < n_max/2 ... see the kernel), padding.
+// (0: L <= 1 and the B1/B2 units, 1: L = 2, 2: L = 3, 3: L = 4), one kernel per group, so
+// that each kernel is register-allocated for its own accumulators.
+constexpr int kUnitGroups = 4;
+__host__ __device__ constexpr int unit_group(int L) { return L <= 1 ? 0 : L - 1; }
+// ints per adjoint unit record: type, L (-1: a B1/B2 unit), first pair (B1/B2: the label
+// n1), end pair, half (0: the other pair label n < (n_max + 1)/2, 1: the rest), first and
+// end entry of the unit's pair stream, padding.
 constexpr int kUnitRec = 8;
+// Words per entry of the adjoint pair stream (float32 path): one entry per pair of a unit
+// that has third blocks of the unit's degree in the unit's half, holding
+// [0] off1, [1] off2, [2] run label n, [3] other label n, [4] first radial index n3 of the
+// third blocks, [5..7] padding, [8 + n3] c1 and [20 + n3] c2 of the triple (n3 < 12; zero
+// where there is no triple), so that a pair costs one batch of independent scalar loads.
+constexpr int kAdjRec = 32;
+constexpr int kAdjC1 = 8, kAdjC2 = 20;
 
 template <class T>
 struct alignas(2 * sizeof(T)) Coef2 {
@@ -46,6 +54,8 @@ struct AceTables {
   const T* b2_c2;
   int npairs;
   const int* units;       // [nunits][kUnitRec]
+  const int* adj_i;       // [nentries][kAdjRec] adjoint pair stream (float32 tables only)
+  const float* adj_f;     // the same stream, read as coefficients
   const int* wave_units;  // [kUnitGroups][kUnitWaves + 1] offsets, then unit indices per wave
 };
 
@@ -57,7 +67,7 @@ struct apx_ace_model {
   long long n_basis = 0;
   int npairs = 0, ntrip = 0, nb1 = 0, nb2 = 0;
   long long coupling_terms = 0, triple_width = 0;  // per-atom work counts
-  int group_units[apx::kUnitGroups] = {0, 0, 0};    // adjoint units per launch group
+  int group_units[apx::kUnitGroups] = {};           // adjoint units per launch group
   double r_cut = 5.0, h = 0.5, s_a = 1.0, eps = 0.1;
   int anchored = 0;
   apx_eam_params anchor{};
@@ -67,4 +77,6 @@ struct apx_ace_model {
   apx::AceTables<float> t32{};
   std::vector<double> W;      // host copy [l][n][k]
   std::vector<int> t_v, b1_v, b2_v;  // basis index of every coefficient slot (host)
+  std::vector<int> adj_ent;          // adjoint stream entries: off1, off2, run, other, n30, first triple
+  apx::DevBuf adj;                   // adjoint pair stream (kAdjRec words per entry)
 };

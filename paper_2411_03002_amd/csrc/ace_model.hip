@@ -37,8 +37,8 @@ bool coupled(int l1, int l2, int l3) { return ((l1 + l2 + l3) % 2 == 0) && l3 >=
 
 struct Catalogue {
   long long n_basis = 0;
-  std::vector<int> pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units;
-  int group_units[kUnitGroups] = {0, 0, 0};
+  std::vector<int> pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units, adj_ent;
+  int group_units[kUnitGroups] = {};
   int ntrip = 0;
   long long coupling_terms = 0, triple_width = 0;
 };
@@ -165,6 +165,24 @@ Catalogue build_catalogue(int n_max, int l_max) {
       ucost.push_back(cst);
     }
   }
+  // the pair stream of every (type, L) unit: the pairs of its half that have third blocks
+  // of degree L, in pair order (by run label, then other label)
+  for (auto& u : units) {
+    if (u[1] < 0) continue;
+    const int L = u[1], type = u[0];
+    const int l1 = type / LL, l2 = type % LL;
+    u[5] = (int)(c.adj_ent.size() / 6);
+    for (int k = u[2]; k < u[3]; ++k) {
+      const int* r = tmp[k].rec;
+      if (r[5 + L] <= r[4 + L]) continue;
+      const int nrun = l1 >= l2 ? r[3] : r[15];
+      const int noth = l1 >= l2 ? r[15] : r[3];
+      if ((noth < half_n) != (u[4] == 0)) continue;
+      const int n30 = (r[10 + L] - L * L) / (LL * LL);
+      c.adj_ent.insert(c.adj_ent.end(), {r[0], r[1], nrun, noth, n30, r[4 + L]});
+    }
+    u[6] = (int)(c.adj_ent.size() / 6);
+  }
   // each launch group is dealt to the waves separately, longest processing time first
   for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());
   c.wave_units.assign(kUnitGroups * (kUnitWaves + 1), 0);
@@ -242,6 +260,26 @@ static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalo
   offs[7] = out.size();
 }
 
+// The adjoint pair stream with the coefficients of the current model (kAdjRec words per
+// entry; coefficients as float32).
+static std::vector<int32_t> adjoint_stream(const apx_ace_model* m, const double* c1, const double* c2) {
+  const size_t ne = m->adj_ent.size() / 6;
+  std::vector<int32_t> out(ne * kAdjRec, 0);
+  for (size_t e = 0; e < ne; ++e) {
+    const int* a = m->adj_ent.data() + 6 * e;
+    int32_t* o = out.data() + e * kAdjRec;
+    for (int k = 0; k < 5; ++k) o[k] = a[k];
+    const int n30 = a[4], q0 = a[5];
+    for (int n3 = n30; n3 < m->n_max; ++n3) {
+      const int v = m->t_v[q0 + n3 - n30];
+      const float f1 = (float)c1[v], f2 = (float)c2[v];
+      std::memcpy(o + kAdjC1 + n3, &f1, 4);
+      std::memcpy(o + kAdjC2 + n3, &f2, 4);
+    }
+  }
+  return out;
+}
+
 template <class T>
 static void set_tables(AceTables<T>& t, const T* base, const size_t* offs, const int* ib, const size_t* ioffs) {
   t.Wp = base + offs[0];
@@ -298,6 +336,7 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   m->t_v = c.t_v;
   m->b1_v = c.b1_v;
   m->b2_v = c.b2_v;
+  m->adj_ent = c.adj_ent;
   // integer tables
   std::vector<int> ib;
   size_t ioffs[8];
@@ -327,6 +366,17 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   set_tables(m->t32, m->reals32.as<float>(), o32, m->ints.as<int>(), ioffs);
   m->t64.npairs = m->npairs;
   m->t32.npairs = m->npairs;
+  const std::vector<int32_t> adj = adjoint_stream(m, d->c1, d->c2);
+  if (m->adj.ensure(adj.size() * 4 + 4) != hipSuccess) {
+    delete m;
+    return fail(ctx, APX_ENOMEM, "ACE table allocation failed");
+  }
+  if (hipMemcpy(m->adj.p, adj.data(), adj.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    delete m;
+    return fail(ctx, APX_EDEVICE, "ACE table upload failed");
+  }
+  m->t32.adj_i = m->adj.as<int>();
+  m->t32.adj_f = m->adj.as<float>();
   *out = m;
   return APX_OK;
 }
@@ -348,6 +398,8 @@ extern "C" apx_status apx_ace_model_set_coeffs(apx_ctx* ctx, apx_ace_model* m, c
   APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
   APX_HIP(ctx, hipMemcpy(m->reals64.p, r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
   APX_HIP(ctx, hipMemcpy(m->reals32.p, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice));
+  const std::vector<int32_t> adj = adjoint_stream(m, c1, c2);
+  APX_HIP(ctx, hipMemcpy(m->adj.p, adj.data(), adj.size() * 4, hipMemcpyHostToDevice));
   return APX_OK;
 }
 
