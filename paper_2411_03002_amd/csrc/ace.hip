@@ -1109,12 +1109,14 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
     }
     const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
-    const size_t ldse = sizeof(T) * ((size_t)na * (TILE + 1) + NWU * 4 * TILE);
+    // the energy pass needs few registers: 8 waves share a staged tile
+    constexpr int NWE = 8;
+    const size_t ldse = sizeof(T) * ((size_t)na * (TILE + 1) + NWE * 4 * TILE);
     const size_t ldsa = sizeof(T) * (size_t)na * (TILE + 1);
     auto energy = [&](auto kern) -> apx_status {
       if (ensure_lds(ctx, (const void*)kern, ldse) != APX_OK) return APX_EDEVICE;
       ProfScope ps(ctx, "ace.energy");
-      kern<<<nblk, NWU * 64, ldse, ctx->stream>>>(sc.A, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
+      kern<<<nblk, NWE * 64, ldse, ctx->stream>>>(sc.A, n_act, na, m->n_max, tb, m->nb1, m->nb2, (T)m->eps,
                                                   sc.e_anch, active, e_site, sc.fp);
       APX_LAUNCH_CHECK(ctx);
       return APX_OK;
@@ -1136,7 +1138,7 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
     };
     apx_status s;
 #define APX_PRODUCTS(LM_, NM_)                                                                          \
-  s = energy(k_ace_energy<T, LM_, NM_, TILE, NWU, true>);                                               \
+  s = energy(k_ace_energy<T, LM_, NM_, TILE, NWE, true>);                                               \
   if (s == APX_OK)                                                                                      \
     s = adjoint(k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>,     \
                 k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 3>);
