@@ -91,7 +91,8 @@ typedef struct {
 /* Build `nl` for `atoms` with cutoff `r_list`.  Periodic dimensions need
  * r_list < L/2.  If some row needs more than nl->max_nb entries the call returns
  * APX_ECAPACITY and stores the largest row length in *needed (host, required; (sync)).
- * Rows are then truncated.  Otherwise *needed receives the largest row length. */
+ * The rows' contents are then unspecified.  Otherwise *needed receives the largest row
+ * length. */
 apx_status apx_build_neighbors(apx_ctx* ctx, const apx_atoms* atoms, double r_list,
                                apx_nlist* nl, int32_t* needed);
 

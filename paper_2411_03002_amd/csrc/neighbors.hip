@@ -8,7 +8,7 @@
 namespace apx {
 
 constexpr int kNbThreads = 64;  // one wave per block: each thread owns one row in LDS
-constexpr int kNbCap = 128;     // row capacity held in LDS
+constexpr int kNbCap = 128;     // largest row capacity (max_nb)
 constexpr int kBatch = 8;       // candidates whose loads are issued together
 
 // One thread per atom.  Candidate atoms come from the 27 (or fewer, for grids with fewer
@@ -19,8 +19,11 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
                                                       const int* __restrict__ cell_atoms, double rl2,
                                                       int max_nb, int* __restrict__ count,
                                                       int* __restrict__ idx, int* __restrict__ flags) {
-  __shared__ int row[kNbCap][kNbThreads];
+  // the thread's row, max_nb entries in LDS (dynamic size); entries beyond max_nb are
+  // only counted, so the caller learns the length it needs
+  extern __shared__ int row_lds[];
   const int t = threadIdx.x;
+  auto row = [&](int k) -> int& { return row_lds[k * kNbThreads + t]; };
   const int i = xcd_block(blockIdx.x, gridDim.x) * kNbThreads + t;
   const bool valid = i < n;
   int cnt = 0;
@@ -76,13 +79,13 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
               const double dz = min_image(pz[q] - zi, Lz, hz, g.per[2]);
               const double r2 = sq_dist_exact(dx, dy, dz);
               if (j != i && r2 < rl2) {
-                if (cnt < kNbCap) {
+                if (cnt < max_nb) {
                   int k = cnt;
-                  while (k > 0 && row[k - 1][t] > j) {
-                    row[k][t] = row[k - 1][t];
+                  while (k > 0 && row(k - 1) > j) {
+                    row(k) = row(k - 1);
                     --k;
                   }
-                  row[k][t] = j;
+                  row(k) = j;
                 }
                 ++cnt;
               }
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(kNbThreads) k_build(const double* __restrict__
   if (!valid) return;
   count[i] = cnt;
   const int m = cnt < max_nb ? cnt : max_nb;
-  for (int k = 0; k < m; ++k) idx[(size_t)k * n + i] = row[k][t];
+  for (int k = 0; k < m; ++k) idx[(size_t)k * n + i] = row(k);
 }
 
 }  // namespace apx
@@ -134,7 +137,7 @@ extern "C" apx_status apx_build_neighbors(apx_ctx* ctx, const apx_atoms* atoms, 
   }
   if (s != APX_OK) return s;
   ProfScope ps(ctx, "nbr.build");
-  k_build<<<blocks_for(n, kNbThreads), kNbThreads, 0, ctx->stream>>>(
+  k_build<<<blocks_for(n, kNbThreads), kNbThreads, sizeof(int) * kNbThreads * nl->max_nb, ctx->stream>>>(
       atoms->pos, n, g, ctx->cell_start.as<int>(), ctx->cell_atoms.as<int>(), r_list * r_list, nl->max_nb,
       nl->count, nl->idx, ctx->flags.as<int>());
   APX_LAUNCH_CHECK(ctx);
