@@ -801,7 +801,6 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
       run_n = nrun;
     }
     const int o1 = cld(E), o2 = cld(E + 1);
-    const int n30 = cld(E + 4);
     T a[N1], b[N2], P[NL], Pb[NL];
 #pragma unroll
     for (int m = 0; m < N1; ++m) a[m] = As[(o1 + m) * ST + t];
@@ -815,7 +814,9 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
     C::template fwd<T>(a, b, P);
 #pragma unroll
     for (int n3 = 0; n3 < NMAX; ++n3) {
-      if (n3 >= n30 && n3 < n_max) {
+      // the stream's coefficients are zero outside [n30, n_max) and so is A3 beyond
+      // n_max: those terms add exact zeros, which costs less than branching on them
+      {
         const T d = fma(fp, cld(Ec + kAdjC2 + n3), cld(Ec + kAdjC1 + n3));
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
