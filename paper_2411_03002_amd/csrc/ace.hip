@@ -748,9 +748,40 @@ __device__ __forceinline__ X cld(const X* p) {
   return *(const __attribute__((address_space(4))) X*)p;
 }
 
+// The third blocks of degree L in registers, and the flush of their adjoint.
+template <class T, int LMAX, int NMAX, int TILE, int L>
+__device__ __forceinline__ void third_load(const T* __restrict__ As, int n_max, int t, T (&A3)[NMAX][2 * L + 1],
+                                           T (&acc3)[NMAX][2 * L + 1]) {
+  constexpr int ST = TILE + 1;
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) {
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) {
+      acc3[n][m] = T(0);
+      A3[n][m] = n < n_max ? As[(n * P2 + L * L + m) * ST + t] : T(0);
+    }
+  }
+}
+
+template <class T, int LMAX, int NMAX, int TILE, int L>
+__device__ __forceinline__ void third_flush(T* __restrict__ Abt, int n_max, int t, const T (&acc3)[NMAX][2 * L + 1]) {
+  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) {
+    if (n < n_max) {
+#pragma unroll
+      for (int m = 0; m < 2 * L + 1; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m]);
+    }
+  }
+}
+
+// The pairs of one unit (l1, l2, L) for one half of the other label; the third-block
+// registers A3 and their adjoint acc3 are the caller's (shared by the units of one degree).
 template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
 __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                         int eb, int ee, int half, int n_max, int t, T fp) {
+                                         int eb, int ee, int half, int n_max, int t, T fp,
+                                         const T (&A3)[NMAX][2 * L + 1], T (&acc3)[NMAX][2 * L + 1]) {
   using C = Couple3<LMAX, L1, L2, L>;
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
@@ -766,18 +797,8 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   const int obase = half ? hn : 0;
   const int oend = half ? n_max : hn;
   constexpr int NH = (NMAX + 1) / 2;  // labels in a half, at most
-  T acc3[NMAX][NL];
-  T A3[NMAX][NL];  // the unit's third blocks, read once for all its pairs
   T accR[NR];
   T accO[NH][NO];  // adjoint of the other label, by its position in the half
-#pragma unroll
-  for (int n = 0; n < NMAX; ++n) {
-#pragma unroll
-    for (int m = 0; m < NL; ++m) {
-      acc3[n][m] = T(0);
-      A3[n][m] = n < n_max ? As[(n * P2 + L * L + m) * ST + t] : T(0);
-    }
-  }
 #pragma unroll
   for (int h = 0; h < NH; ++h) {
 #pragma unroll
@@ -854,13 +875,16 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
       for (int m = 0; m < NO; ++m) gadd<T, TILE>(Abt, (obase + h) * P2 + LO * LO + m, t, accO[h][m]);
     }
   }
-#pragma unroll
-  for (int n = 0; n < NMAX; ++n) {
-    if (n < n_max) {
-#pragma unroll
-      for (int m = 0; m < NL; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m]);
-    }
-  }
+}
+
+// A unit with third-block registers of its own (the mixed-degree launch group).
+template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
+__device__ __forceinline__ void unit_bwd_own(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
+                                             int eb, int ee, int half, int n_max, int t, T fp) {
+  T A3[NMAX][2 * L + 1], acc3[NMAX][2 * L + 1];
+  third_load<T, LMAX, NMAX, TILE, L>(As, n_max, t, A3, acc3);
+  unit_bwd<T, LMAX, NMAX, TILE, L1, L2, L>(As, Abt, tb, eb, ee, half, n_max, t, fp, A3, acc3);
+  third_flush<T, LMAX, NMAX, TILE, L>(Abt, n_max, t, acc3);
 }
 
 // B1 and B2 adjoint of one first label n1: its B1 entry (entry n1) and its B2 entries,
@@ -997,6 +1021,10 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
   T* Abt = Abg + (size_t)blockIdx.x * na * TILE;
   const int* wu = tb.wave_units;
   const int* lst = wu + kUnitGroups * (NW + 1);
+  // the one third-block degree of groups 1..3 (group 0 holds degrees 0 and 1)
+  constexpr int LG = G > 0 ? G + 1 : 0;
+  T A3[NMAX][2 * LG + 1], acc3[NMAX][2 * LG + 1];
+  if constexpr (G > 0) third_load<T, LMAX, NMAX, TILE, LG>(As, n_max, t, A3, acc3);
   const int ub = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv));
   const int ue = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv + 1));
   for (int k = ub; k < ue; ++k) {
@@ -1013,10 +1041,14 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
       continue;
     }
     const int key = type * (LMAX + 1) + L;
+    // group 0 mixes degrees: each unit keeps its own third-block registers; the other
+    // groups have one degree LG, whose registers persist across the wave's units
 #define APX_UNIT(A_, B_, C_)                                                                              \
   case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
-    if constexpr (unit_group(C_) == G)                                                                    \
-      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp);                 \
+    if constexpr (G == 0 && unit_group(C_) == 0)                                                          \
+      unit_bwd_own<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp);             \
+    else if constexpr (G > 0 && C_ == LG)                                                                 \
+      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp, A3, acc3);       \
     break;
     if constexpr (LMAX == 3) {
       switch (key) { APX_UNIT_CASES_3(APX_UNIT) default: break; }
@@ -1025,6 +1057,7 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
     }
 #undef APX_UNIT
   }
+  if constexpr (G > 0) third_flush<T, LMAX, NMAX, TILE, LG>(Abt, n_max, t, acc3);
 }
 
 template <class T>
