@@ -877,16 +877,6 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   }
 }
 
-// A unit with third-block registers of its own (the mixed-degree launch group).
-template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
-__device__ __forceinline__ void unit_bwd_own(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                             int eb, int ee, int half, int n_max, int t, T fp) {
-  T A3[NMAX][2 * L + 1], acc3[NMAX][2 * L + 1];
-  third_load<T, LMAX, NMAX, TILE, L>(As, n_max, t, A3, acc3);
-  unit_bwd<T, LMAX, NMAX, TILE, L1, L2, L>(As, Abt, tb, eb, ee, half, n_max, t, fp, A3, acc3);
-  third_flush<T, LMAX, NMAX, TILE, L>(Abt, n_max, t, acc3);
-}
-
 // B1 and B2 adjoint of one first label n1: its B1 entry (entry n1) and its B2 entries,
 // stored in catalogue order (n1, n2 >= n1, l).  For each l the adjoint of block (n1, l) is
 // accumulated over n2 in registers, the adjoint of block (n2, l) is added per entry.
@@ -1021,10 +1011,10 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
   T* Abt = Abg + (size_t)blockIdx.x * na * TILE;
   const int* wu = tb.wave_units;
   const int* lst = wu + kUnitGroups * (NW + 1);
-  // the one third-block degree of groups 1..3 (group 0 holds degrees 0 and 1)
-  constexpr int LG = G > 0 ? G + 1 : 0;
+  // the third-block degree of the group's units
+  constexpr int LG = G;
   T A3[NMAX][2 * LG + 1], acc3[NMAX][2 * LG + 1];
-  if constexpr (G > 0) third_load<T, LMAX, NMAX, TILE, LG>(As, n_max, t, A3, acc3);
+  third_load<T, LMAX, NMAX, TILE, LG>(As, n_max, t, A3, acc3);
   const int ub = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv));
   const int ue = __builtin_amdgcn_readfirstlane(cld(wu + G * (NW + 1) + wv + 1));
   for (int k = ub; k < ue; ++k) {
@@ -1041,13 +1031,11 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
       continue;
     }
     const int key = type * (LMAX + 1) + L;
-    // group 0 mixes degrees: each unit keeps its own third-block registers; the other
-    // groups have one degree LG, whose registers persist across the wave's units
+    // every unit of the group has degree LG; the third-block registers persist across the
+    // wave's units
 #define APX_UNIT(A_, B_, C_)                                                                              \
   case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
-    if constexpr (G == 0 && unit_group(C_) == 0)                                                          \
-      unit_bwd_own<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp);             \
-    else if constexpr (G > 0 && C_ == LG)                                                                 \
+    if constexpr (C_ == LG)                                                                               \
       unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp, A3, acc3);       \
     break;
     if constexpr (LMAX == 3) {
@@ -1057,7 +1045,7 @@ __global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict_
     }
 #undef APX_UNIT
   }
-  if constexpr (G > 0) third_flush<T, LMAX, NMAX, TILE, LG>(Abt, n_max, t, acc3);
+  third_flush<T, LMAX, NMAX, TILE, LG>(Abt, n_max, t, acc3);
 }
 
 template <class T>
@@ -1155,10 +1143,11 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
       return APX_OK;
     };
-    auto adjoint = [&](auto k0, auto k1, auto k2, auto k3) -> apx_status {
+    auto adjoint = [&](auto k0, auto k1, auto k2, auto k3, auto k4) -> apx_status {
       ProfScope ps(ctx, "ace.adjoint");
-      static_assert(kUnitGroups == 4, "one kernel per launch group");
-      const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2, (const void*)k3};
+      static_assert(kUnitGroups == 5, "one kernel per launch group");
+      const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2, (const void*)k3,
+                                     (const void*)k4};
       for (int g = 0; g < kUnitGroups; ++g) {
         if (m->group_units[g] == 0) continue;
         if (ensure_lds(ctx, ks[g], ldsa) != APX_OK) return APX_EDEVICE;
@@ -1166,6 +1155,7 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
         if (g == 1) k1<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         if (g == 2) k2<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         if (g == 3) k3<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 4) k4<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         APX_LAUNCH_CHECK(ctx);
       }
       return APX_OK;
@@ -1175,7 +1165,8 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   s = energy(k_ace_energy<T, LM_, NM_, TILE, NWE, true>);                                               \
   if (s == APX_OK)                                                                                      \
     s = adjoint(k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>,     \
-                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 3>);
+                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 3>,     \
+                k_ace_adjoint<T, LM_, NM_, TILE, NWU, 4>);
     if constexpr (LMAX == 3) {
       if (m->n_max <= 8) {
         APX_PRODUCTS(3, 8)

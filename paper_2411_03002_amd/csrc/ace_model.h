@@ -15,11 +15,11 @@ constexpr int kAceWaves64 = 8;
 constexpr int kPairRec = 16;
 // Waves per block of the unit-adjoint product kernels (float32).
 constexpr int kUnitWaves = 4;
-// The adjoint units are launched in groups by the degree L of their third block
-// (0: L <= 1 and the B1/B2 units, 1: L = 2, 2: L = 3, 3: L = 4), one kernel per group, so
-// that each kernel is register-allocated for its own accumulators.
-constexpr int kUnitGroups = 4;
-__host__ __device__ constexpr int unit_group(int L) { return L <= 1 ? 0 : L - 1; }
+// The adjoint units are launched in groups by the degree L of their third block (group L;
+// the B1/B2 units join group 0), one kernel per group, so that each kernel is
+// register-allocated for its own accumulators and keeps one degree's third blocks.
+constexpr int kUnitGroups = 5;
+__host__ __device__ constexpr int unit_group(int L) { return L < 0 ? 0 : L; }
 // ints per adjoint unit record: type, L (-1: a B1/B2 unit), first pair (B1/B2: the label
 // n1), end pair, half (0: the other pair label n < (n_max + 1)/2, 1: the rest), first and
 // end entry of the unit's pair stream, padding.
