@@ -990,11 +990,13 @@ __global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag
   }
 }
 
+// Degrees 0..2 run at two waves per SIMD (degree 2 spills a few registers, which costs
+// less than the lost occupancy); degrees 3 and 4 need one wave per SIMD.
 // Adjoint of the product basis for the units of one launch group G: the tile's atomic
 // base is staged again, the embedding slope is read from the energy pass, and every
 // wave runs its units (see unit_bwd), adding to the tile's adjoint in global memory.
 template <class T, int LMAX, int NMAX, int TILE, int NW, int G>
-__global__ void __launch_bounds__(NW * 64, 1) k_ace_adjoint(const T* __restrict__ Ag, T* __restrict__ Abg,
+__global__ void __launch_bounds__(NW * 64, G <= 2 ? 2 : 1) k_ace_adjoint(const T* __restrict__ Ag, T* __restrict__ Abg,
                                                             int n_act, int na, int n_max, AceTables<T> tb, int nb1,
                                                             const T* __restrict__ fp_in) {
   static_assert(NW == kUnitWaves, "the unit tables are dealt to kUnitWaves waves");
