@@ -877,35 +877,35 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   }
 }
 
-// B1 and B2 adjoint of one first label n1: its B1 entry (entry n1) and its B2 entries,
-// stored in catalogue order (n1, n2 >= n1, l).  For each l the adjoint of block (n1, l) is
-// accumulated over n2 in registers, the adjoint of block (n2, l) is added per entry.
+// B1 and B2 adjoint of one label n, output-stationary.  B2_(n1 n2 l) = sum_m A_n1lm A_n2lm
+// (n1 <= n2, entries stored in catalogue order (n1, n2, l)), so
+//   dE/dA_nlm = sum_n' D_nn'l A_n'lm,  D_nn'l = d_(min, max, l) for n' != n, 2 d_(n n l) for n' = n,
+// with d = c1 + F'(phi2) c2 of the entry; plus the B1 entry of label n.  The label's
+// adjoint is accumulated in registers and added once per (l, m).
 template <class T, int LMAX, int TILE>
 __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                               int nb1, int n_max, int n1, int t, T fp) {
+                                               int nb1, int n_max, int n, int t, T fp) {
   constexpr int ST = TILE + 1;
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
-  if (n1 < nb1) gadd<T, TILE>(Abt, cld(tb.b1_off + n1), t, fma(fp, cld(tb.b1_c2 + n1), cld(tb.b1_c1 + n1)));
-  // entries of the labels before n1: sum over n' < n1 of (n_max - n')(l_max + 1)
-  const int base = (LMAX + 1) * (n1 * n_max - n1 * (n1 - 1) / 2);
+  // first entry of the labels n1: sum over n' < n1 of (n_max - n')(l_max + 1)
+  auto base = [&](int n1) { return (LMAX + 1) * (n1 * n_max - n1 * (n1 - 1) / 2); };
 #pragma unroll
   for (int l = 0; l <= LMAX; ++l) {
-    T accR[2 * l + 1];
+    T acc[2 * l + 1];
 #pragma unroll
-    for (int m = 0; m < 2 * l + 1; ++m) accR[m] = T(0);
-    for (int n2 = n1; n2 < n_max; ++n2) {
-      const int e = base + (n2 - n1) * (LMAX + 1) + l;
-      const T d = fma(fp, cld(tb.b2_c2 + e), cld(tb.b2_c1 + e));
-      const int o1 = n1 * P2 + l * l, o2 = n2 * P2 + l * l;
+    for (int m = 0; m < 2 * l + 1; ++m) acc[m] = T(0);
+    for (int np = 0; np < n_max; ++np) {
+      const int n1 = np < n ? np : n, n2 = np < n ? n : np;
+      const int e = base(n1) + (n2 - n1) * (LMAX + 1) + l;
+      T d = fma(fp, cld(tb.b2_c2 + e), cld(tb.b2_c1 + e));
+      if (np == n) d += d;
+      const int o = np * P2 + l * l;
 #pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) {
-        const T x1 = As[(o1 + m) * ST + t], x2 = As[(o2 + m) * ST + t];
-        accR[m] = fma(d, x2, accR[m]);
-        gadd<T, TILE>(Abt, o2 + m, t, d * x1);
-      }
+      for (int m = 0; m < 2 * l + 1; ++m) acc[m] = fma(d, As[(o + m) * ST + t], acc[m]);
     }
+    if (l == 0 && n < nb1) acc[0] += fma(fp, cld(tb.b1_c2 + n), cld(tb.b1_c1 + n));
 #pragma unroll
-    for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n1 * P2 + l * l + m, t, accR[m]);
+    for (int m = 0; m < 2 * l + 1; ++m) gadd<T, TILE>(Abt, n * P2 + l * l + m, t, acc[m]);
   }
 }
 
