@@ -19,6 +19,7 @@
 //                    per neighbour the gradient of sum Abar'' g_k S_lm, scattered as
 //                    F_j -= w_i dE_i/dr_ij, F_i += w_i dE_i/dr_ij (float64 atomics).
 #include <cmath>
+#include <type_traits>
 
 #include "ace_coupling_gen.h"
 #include "ace_model.h"
@@ -1187,26 +1188,38 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   }
   }
   if (!use_units) {
-  constexpr int NW = sizeof(T) == 4 ? kAceWaves32 : kAceWaves64;
-  const size_t lds2 = sizeof(T) * ((size_t)2 * na * (TILE + 1) + NW * 4 * TILE + TILE);
-  if (lds2 > (size_t)lds_max)
-    return fail(ctx, APX_EINVAL, "ACE tile needs %zu bytes of LDS, the device allows %d (reduce n_max)", lds2, lds_max);
-  const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
-  {
-  ProfScope ps(ctx, "ace.products");
-  if (dc1) {
-    auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, true>;
-    if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
-    kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
-                                               sc.e_anch, active, w, e_site, dc1, dc2);
-  } else {
-    auto kern = k_ace_products<T, LMAX, TILE, NW, sizeof(T) == 4, false>;
-    if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
-    kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
-                                               sc.e_anch, active, w, e_site, nullptr, nullptr);
-  }
-  APX_LAUNCH_CHECK(ctx);
-  }
+    // the LDS version (float64, or float32 with coefficient gradients) stages the tile's
+    // A and its adjoint; for large bases the tile is halved so that both fit
+    constexpr int NW = sizeof(T) == 4 ? kAceWaves32 : kAceWaves64;
+    auto lds_for = [&](int tl) { return sizeof(T) * ((size_t)2 * na * (tl + 1) + NW * 4 * tl + tl); };
+    auto products = [&](auto tile_c) -> apx_status {
+      constexpr int TL = decltype(tile_c)::value;
+      const size_t lds2 = lds_for(TL);
+      const unsigned nblk = (unsigned)((n_act + TL - 1) / TL);
+      ProfScope ps(ctx, "ace.products");
+      if (dc1) {
+        auto kern = k_ace_products<T, LMAX, TL, NW, sizeof(T) == 4, true>;
+        if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
+        kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                                   sc.e_anch, active, w, e_site, dc1, dc2);
+      } else {
+        auto kern = k_ace_products<T, LMAX, TL, NW, sizeof(T) == 4, false>;
+        if (ensure_lds(ctx, (const void*)kern, lds2) != APX_OK) return APX_EDEVICE;
+        kern<<<nblk, NW * 64, lds2, ctx->stream>>>(sc.A, sc.Ab, n_act, na, tb, m->nb1, m->nb2, (T)m->eps,
+                                                   sc.e_anch, active, w, e_site, nullptr, nullptr);
+      }
+      APX_LAUNCH_CHECK(ctx);
+      return APX_OK;
+    };
+    apx_status s;
+    if (lds_for(TILE) <= (size_t)lds_max)
+      s = products(std::integral_constant<int, TILE>{});
+    else if (lds_for(TILE / 2) <= (size_t)lds_max)
+      s = products(std::integral_constant<int, TILE / 2>{});
+    else
+      return fail(ctx, APX_EINVAL, "ACE tile needs %zu bytes of LDS, the device allows %d (reduce n_max)",
+                  lds_for(TILE / 2), lds_max);
+    if (s != APX_OK) return s;
   }
   const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
   ProfScope ps(ctx, "ace.force");

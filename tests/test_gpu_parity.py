@@ -151,9 +151,13 @@ def test_eam_parity(ops_ctx, name):
     assert np.allclose(e["f"].cpu().numpy(), ref["f_eam"], atol=FTOL, rtol=0)
 
 
+# the library specialises its product kernels by (l_max, n_max <= 8 / 12) and
+# (l_max 4, n_max <= 10 / 12): one case per specialisation
 ACE_CASES = {
     "cfg0_8_3_random": ("cfg0", 8, 3, False),
+    "slab_9_3_anchored": ("slab100_4x4x6", 9, 3, True),
     "slab_10_4_anchored": ("slab100_4x4x6", 10, 4, True),
+    "void_12_4_random": ("void_bulk8", 12, 4, False),
 }
 
 
