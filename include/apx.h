@@ -129,6 +129,40 @@ apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx
                                  double* csp, double* w0, double* w, uint8_t* mask,
                                  int32_t* active, int64_t* n_active);
 
+/* Time-averaged switching: Appendix B eqs. csp_2_i, lambda_1_i, lambda_2_i, lambda_3_i,
+ * lambda_4_i (N_CSP,avg = N_lambda,avg = n_avg; Delta lambda_min = dw_min), in the
+ * precise-weight form w = 1 - lambda.  One call takes one sample at the given positions:
+ *   csp      the instantaneous CSP (as apx_compute_precision; an input with
+ *            APX_PREC_CSP_GIVEN), pushed into csp_ring;
+ *   csp_avg  the mean of the newest min(samples + 1, n_avg) CSP samples;
+ *   w0       the switch of csp_avg, combined with w0_extra by max; frozen atoms 0;
+ *   w_min    w0 spread as in apx_compute_precision, pushed into w_ring;
+ *   w_avg    (nullable) the mean of the newest w_min samples;
+ *   w        in: the filtered weight returned by the previous call (ignored on the
+ *            first); out: w_avg where |w_avg - w_prev| >= dw_min or w_avg is 0 or 1,
+ *            else w_prev (on the first call w_avg);
+ *   mask, active, *n_active (host, (sync)) as in apx_compute_precision, from the new w.
+ * A mean adds its samples newest first from 0.0 and divides by their number.  The rings
+ * are caller-owned device arrays [n_avg][n] (slot-major) whose contents the calls keep;
+ * `samples` counts the samples taken (0 before the first call) and each successful call
+ * advances it by one; the ring slot of a call is samples % n_avg.  All arrays are device
+ * arrays of length n.  EINVAL: n_avg outside 1..4096, samples < 0, dw_min < 0 or NaN,
+ * missing rings, csp_avg or w_min, or any condition of apx_compute_precision. */
+typedef struct {
+  int32_t n_avg;      /* samples per moving mean */
+  int32_t reserved;
+  int64_t samples;    /* samples taken so far */
+  double dw_min;      /* minimum step of the filtered weight */
+  double* csp_ring;   /* device [n_avg][n] */
+  double* w_ring;     /* device [n_avg][n] */
+} apx_avg_state;
+
+apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                     const apx_prec_params* p, apx_avg_state* st,
+                                     const double* w0_extra, double* csp, double* csp_avg,
+                                     double* w0, double* w_min, double* w_avg, double* w,
+                                     uint8_t* mask, int32_t* active, int64_t* n_active);
+
 /* ------------------------------------------------------------------- EAM */
 /* Sec. III B eq. energy_eam: E_i = F(rho_i) + 1/2 sum_j phi(r_ij), rho_i = sum_j rho(r_ij)
  * over r_ij < r_cut, with phi(r) = A exp(-alpha(r - r0)) psi((r - r_cut)/h),
@@ -211,10 +245,13 @@ typedef struct {
   int32_t ace_precision;   /* APX_FP64 or APX_FP32 */
   int32_t mode;            /* APX_MODE_* */
   int32_t indenter;        /* 1: spherical indenter on */
-  int32_t reserved;
+  int32_t avg_samples;     /* adaptive mode: 0 instantaneous weights; n > 0 time-averaged
+                              weights (apx_compute_precision_avg) over n samples, one
+                              sample per weight update, the history restarted by apx_md_init */
   double ind_radius, ind_k;  /* R (A), K (eV/A^3): U = K/3 (R - d)^3, force K (R - d)^2 */
   double ind_center[3];      /* centre at step 0 */
   double ind_velocity[3];    /* A/ps */
+  double avg_dw_min;         /* minimum step of the time-averaged weight */
 } apx_md_params;
 
 typedef struct {

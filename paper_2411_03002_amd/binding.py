@@ -56,8 +56,14 @@ class AceDesc(C.Structure):
 class MdParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("mass", C.c_double), ("skin", C.c_double), ("max_nb", C.c_int32),
                 ("precision_every", C.c_int32), ("ace_precision", C.c_int32), ("mode", C.c_int32),
-                ("indenter", C.c_int32), ("reserved", C.c_int32), ("ind_radius", C.c_double),
-                ("ind_k", C.c_double), ("ind_center", C.c_double * 3), ("ind_velocity", C.c_double * 3)]
+                ("indenter", C.c_int32), ("avg_samples", C.c_int32), ("ind_radius", C.c_double),
+                ("ind_k", C.c_double), ("ind_center", C.c_double * 3), ("ind_velocity", C.c_double * 3),
+                ("avg_dw_min", C.c_double)]
+
+
+class AvgState(C.Structure):
+    _fields_ = [("n_avg", C.c_int32), ("reserved", C.c_int32), ("samples", C.c_int64), ("dw_min", C.c_double),
+                ("csp_ring", _P), ("w_ring", _P)]
 
 
 class MdStats(C.Structure):
@@ -82,6 +88,9 @@ PROTOTYPES = {
     "apx_build_neighbors": (C.c_int32, [_P, C.POINTER(Atoms), C.c_double, C.POINTER(NList), C.POINTER(C.c_int32)]),
     "apx_compute_precision": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), C.POINTER(PrecParams), _P,
                                           _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
+    "apx_compute_precision_avg": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), C.POINTER(PrecParams),
+                                              C.POINTER(AvgState), _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                              C.POINTER(C.c_int64)]),
     "apx_eam_forces": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), C.POINTER(EamParams), _P, _P, _P, _P]),
     "apx_ace_num_basis": (C.c_int64, [C.c_int32, C.c_int32]),
     "apx_ace_model_create": (C.c_int32, [_P, C.POINTER(AceDesc), C.POINTER(_P)]),

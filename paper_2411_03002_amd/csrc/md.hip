@@ -134,6 +134,8 @@ struct apx_md {
   apx_mlp* mlp = nullptr;  // learned criterion (optional)
   double tau_lo = 0.0, tau_hi = 0.0;
   DevBuf feat, pred, w0x;
+  DevBuf csp_ring, w_ring, csp_avg, w_min;  // time-averaged weights (avg_samples > 0)
+  long long avg_taken = 0;                  // samples in the rings since apx_md_init
   hipEvent_t ev[6] = {};
   double t_acc[5] = {0, 0, 0, 0, 0};
 };
@@ -170,6 +172,27 @@ apx_status md_rebuild(apx_md* md, const double* pos) {
   k_copy_d<<<blocks_for(m3, 256), 256, 0, ctx->stream>>>(m3, pos, md->xref.as<double>());
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
+}
+
+// The criterion's weights from the given parameters: instantaneous, or one sample of the
+// time-averaged pipeline (w holds the previous filtered weights).
+apx_status md_precision(apx_md* md, const apx_nlist& nl, const apx_prec_params& p, const double* w0x, double* w,
+                        int64_t* na) {
+  apx_ctx* ctx = md->ctx;
+  if (md->p.avg_samples <= 0)
+    return apx_compute_precision(ctx, &md->atoms, &nl, &p, w0x, md->csp.as<double>(), md->w0.as<double>(), w,
+                                 md->mask.as<uint8_t>(), md->active.as<int>(), na);
+  apx_avg_state st{};
+  st.n_avg = md->p.avg_samples;
+  st.samples = md->avg_taken;
+  st.dw_min = md->p.avg_dw_min;
+  st.csp_ring = md->csp_ring.as<double>();
+  st.w_ring = md->w_ring.as<double>();
+  apx_status s = apx_compute_precision_avg(ctx, &md->atoms, &nl, &p, &st, w0x, md->csp.as<double>(),
+                                           md->csp_avg.as<double>(), md->w0.as<double>(), md->w_min.as<double>(),
+                                           nullptr, w, md->mask.as<uint8_t>(), md->active.as<int>(), na);
+  md->avg_taken = st.samples;
+  return s;
 }
 
 apx_status md_weights(apx_md* md, const double* pos, double* w) {
@@ -212,14 +235,12 @@ apx_status md_weights(apx_md* md, const double* pos, double* w) {
     if (s != APX_OK) return s;
     apx_prec_params p1 = md->prec;
     p1.flags = APX_PREC_CSP_GIVEN;
-    s = apx_compute_precision(ctx, &md->atoms, &nl, &p1, md->w0x.as<double>(), md->csp.as<double>(),
-                              md->w0.as<double>(), w, md->mask.as<uint8_t>(), md->active.as<int>(), &na);
+    s = md_precision(md, nl, p1, md->w0x.as<double>(), w, &na);
     if (s != APX_OK) return s;
     md->n_active = na;
     return APX_OK;
   }
-  apx_status s = apx_compute_precision(ctx, &md->atoms, &nl, &md->prec, nullptr, md->csp.as<double>(),
-                                       md->w0.as<double>(), w, md->mask.as<uint8_t>(), md->active.as<int>(), &na);
+  apx_status s = md_precision(md, nl, md->prec, nullptr, w, &na);
   if (s != APX_OK) return s;
   md->n_active = na;
   return APX_OK;
@@ -290,6 +311,8 @@ extern "C" apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const 
   if (p->mode == APX_MODE_ADAPTIVE && !prec) return fail(ctx, APX_EINVAL, "adaptive mode needs precision params");
   if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->skin >= 0.0)) return fail(ctx, APX_EINVAL, "dt, mass, skin");
   if (p->max_nb < 1 || p->max_nb > 128) return fail(ctx, APX_EINVAL, "max_nb must be in 1..128");
+  if (p->avg_samples < 0 || p->avg_samples > 4096) return fail(ctx, APX_EINVAL, "avg_samples must be in 0..4096");
+  if (p->avg_samples > 0 && !(p->avg_dw_min >= 0.0)) return fail(ctx, APX_EINVAL, "avg_dw_min must be >= 0");
   apx_md* md = new apx_md();
   md->ctx = ctx;
   md->p = *p;
@@ -316,6 +339,11 @@ extern "C" apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const 
             md->e_site.ensure(sizeof(double) * n) == hipSuccess && md->f_eam.ensure(sizeof(double) * 3 * n) == hipSuccess &&
             md->f_ace.ensure(sizeof(double) * 3 * n) == hipSuccess && md->rho.ensure(sizeof(double) * n) == hipSuccess &&
             md->scal.ensure(sizeof(double) * 8) == hipSuccess;
+  if (ok && p->mode == APX_MODE_ADAPTIVE && p->avg_samples > 0) {
+    const size_t ring = sizeof(double) * (size_t)p->avg_samples * n;
+    ok = md->csp_ring.ensure(ring) == hipSuccess && md->w_ring.ensure(ring) == hipSuccess &&
+         md->csp_avg.ensure(sizeof(double) * n) == hipSuccess && md->w_min.ensure(sizeof(double) * n) == hipSuccess;
+  }
   if (!ok) {
     delete md;
     return fail(ctx, APX_ENOMEM, "integrator buffers");
@@ -348,6 +376,7 @@ extern "C" apx_status apx_md_init(apx_md* md, const double* pos, double* f, doub
   if (!pos || !f || !w) return fail(ctx, APX_EINVAL, "pos, f and w are required");
   apx_status s = md_rebuild(md, pos);
   if (s != APX_OK) return s;
+  md->avg_taken = 0;
   s = md_weights(md, pos, w);
   if (s != APX_OK) return s;
   s = md_forces(md, pos, w, f, md->step * md->p.dt, false);

@@ -9,6 +9,7 @@ namespace apx {
 
 constexpr int kMaxM = 16;     // N + N_buffer
 constexpr int kMaxHalf = 8;   // N / 2
+constexpr int kMaxAvg = 4096; // samples per moving mean
 
 struct PrecDev {
   int n_nn, m, half, kind;
@@ -248,6 +249,71 @@ __global__ void k_compact(int n, const int* __restrict__ flag, const int* __rest
   if (flag[i]) out[pos_[i]] = i;
 }
 
+// Time-averaged switching.  A ring of n_avg samples per atom, slot-major ([slot][n], so
+// each slot is read coalesced); the sample of this call goes to `slot` and the mean adds
+// the m newest samples newest first, starting from 0.0, then divides by m.
+__device__ __forceinline__ double ring_mean(const double* __restrict__ ring, size_t n, int i, int slot, int n_avg,
+                                            int m, double newest) {
+#pragma clang fp contract(off)
+  double acc = 0.0;
+  acc = acc + newest;
+  int s = slot;
+  for (int j = 1; j < m; ++j) {
+    s = s == 0 ? n_avg - 1 : s - 1;
+    acc = acc + ring[(size_t)s * n + i];
+  }
+  return acc / (double)m;
+}
+
+// eq. csp_2_i then eq. lambda_1_i: pushes the CSP sample, averages, switches; w0 seeds
+// the spreading target w.
+__global__ void k_avg_csp(int n, const uint8_t* __restrict__ frozen, PrecDev p, const double* __restrict__ w0_extra,
+                          const double* __restrict__ csp, double* __restrict__ ring, int slot, int n_avg, int m,
+                          double* __restrict__ csp_avg, double* __restrict__ w0, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double c = csp[i];
+  ring[(size_t)slot * n + i] = c;
+  const double a = ring_mean(ring, (size_t)n, i, slot, n_avg, m, c);
+  csp_avg[i] = a;
+  if (frozen && frozen[i]) {
+    w0[i] = 0.0;
+    w[i] = 0.0;
+    return;
+  }
+  double v0 = switch_w0(a, p);
+  if (w0_extra) {
+    const double e = w0_extra[i];
+    v0 = e > v0 ? e : v0;
+  }
+  w0[i] = v0;
+  w[i] = v0;
+}
+
+// eq. lambda_3_i then eq. lambda_4_i: pushes the spread weight, averages, applies the
+// minimum step against the previous filtered weight (in w), writes the mask.
+__global__ void k_avg_w(int n, const double* __restrict__ w_min, double* __restrict__ ring, int slot, int n_avg, int m,
+                        int first, double dw_min, double* __restrict__ w_avg, double* __restrict__ w,
+                        uint8_t* __restrict__ mask, int* __restrict__ flag) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = w_min[i];
+  ring[(size_t)slot * n + i] = v;
+  const double a = ring_mean(ring, (size_t)n, i, slot, n_avg, m, v);
+  if (w_avg) w_avg[i] = a;
+  double out = a;
+  if (!first) {
+    const double prev = w[i];
+    const bool take = fabs(a - prev) >= dw_min || a == 0.0 || a == 1.0;
+    out = take ? a : prev;
+  }
+  w[i] = out;
+  const int k = out > 0.0 ? 1 : 0;
+  mask[i] = (uint8_t)k;
+  flag[i] = k;
+}
+
 }  // namespace apx
 
 using namespace apx;
@@ -268,11 +334,19 @@ static void spread_stencil(const Grid& g, double r_hi, SpreadDev& s) {
   }
 }
 
-extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
-                                            const apx_prec_params* p, const double* w0_extra, double* csp,
-                                            double* w0, double* w, uint8_t* mask, int32_t* active,
-                                            int64_t* n_active) {
-  if (!ctx) return APX_EINVAL;
+namespace {
+
+// The averaging stage of a call: ring slot of this sample, samples in the means, and
+// the buffers (all device, length n or [n_avg][n]).
+struct AvgArgs {
+  int n_avg, slot, m, first;
+  double dw_min;
+  double *csp_ring, *w_ring, *csp_avg, *w_min, *w_avg;
+};
+
+apx_status precision_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_prec_params* p,
+                          const double* w0_extra, double* csp, double* w0, double* w, uint8_t* mask,
+                          int32_t* active, int64_t* n_active, const AvgArgs* avg) {
   apx_status s = check_atoms(ctx, atoms);
   if (s != APX_OK) return s;
   if (!nl || !p || !n_active) return fail(ctx, APX_EINVAL, "nl, params and n_active are required");
@@ -296,18 +370,26 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   pd.csp_lo = p->csp_lo;
   pd.width = p->csp_hi - p->csp_lo;
   pd.rc2 = p->r_cut * p->r_cut;
+  // spreading target: w itself, or the instantaneous weight when averaging
+  double* ws = avg ? avg->w_min : w;
   if (!(p->flags & APX_PREC_CSP_GIVEN)) {
   ProfScope ps(ctx, "prec.csp");
   if (pd.m == 12 && pd.half == 6)
     k_csp<12, 6, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, w);
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, ws);
   else
     k_csp<kMaxM, kMaxHalf, false><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, w);
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, ws);
   APX_LAUNCH_CHECK(ctx);
-  } else {
+  } else if (!avg) {
     ProfScope ps(ctx, "prec.switch");
     k_switch<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, w0, w);
+    APX_LAUNCH_CHECK(ctx);
+  }
+  if (avg) {
+    ProfScope ps(ctx, "prec.avg");
+    k_avg_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, avg->csp_ring,
+                                                           avg->slot, avg->n_avg, avg->m, avg->csp_avg, w0, ws);
     APX_LAUNCH_CHECK(ctx);
   }
   if (p->r_hi > 0.0) {
@@ -333,14 +415,19 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
       ProfScope ps(ctx, "prec.spread");
       k_spread<<<blocks_for(threads, 256), 256, 0, ctx->stream>>>(
           atoms->pos, n, gs, sd, ctx->itmp.as<int>(), nsrc, w0, atoms->frozen, ctx->cell_start.as<int>(),
-          ctx->cell_atoms.as<int>(), reinterpret_cast<unsigned long long*>(w));
+          ctx->cell_atoms.as<int>(), reinterpret_cast<unsigned long long*>(ws));
       APX_LAUNCH_CHECK(ctx);
     }
   }
   APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
   APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
   ProfScope ps(ctx, "prec.compact");
-  k_mask<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, mask, ctx->itmp.as<int>());
+  if (avg)
+    k_avg_w<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ws, avg->w_ring, avg->slot, avg->n_avg, avg->m,
+                                                         avg->first, avg->dw_min, avg->w_avg, w, mask,
+                                                         ctx->itmp.as<int>());
+  else
+    k_mask<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, mask, ctx->itmp.as<int>());
   APX_LAUNCH_CHECK(ctx);
   s = scan_exclusive(ctx, ctx->itmp.as<int>(), n, ctx->itmp2.as<int>());
   if (s != APX_OK) return s;
@@ -351,4 +438,41 @@ extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms
   if (s != APX_OK) return s;
   *n_active = na;
   return APX_OK;
+}
+
+}  // namespace
+
+extern "C" apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                            const apx_prec_params* p, const double* w0_extra, double* csp,
+                                            double* w0, double* w, uint8_t* mask, int32_t* active,
+                                            int64_t* n_active) {
+  return precision_impl(ctx, atoms, nl, p, w0_extra, csp, w0, w, mask, active, n_active, nullptr);
+}
+
+extern "C" apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                                const apx_prec_params* p, apx_avg_state* st,
+                                                const double* w0_extra, double* csp, double* csp_avg, double* w0,
+                                                double* w_min, double* w_avg, double* w, uint8_t* mask,
+                                                int32_t* active, int64_t* n_active) {
+  if (!ctx) return APX_EINVAL;
+  if (!st || !atoms) return fail(ctx, APX_EINVAL, "atoms and the averaging state are required");
+  if (st->n_avg < 1 || st->n_avg > kMaxAvg) return fail(ctx, APX_EINVAL, "n_avg must be in 1..%d", kMaxAvg);
+  if (st->samples < 0) return fail(ctx, APX_EINVAL, "samples must be >= 0");
+  if (!(st->dw_min >= 0.0)) return fail(ctx, APX_EINVAL, "dw_min must be >= 0");
+  if (atoms->n > 0 && (!st->csp_ring || !st->w_ring || !csp_avg || !w_min))
+    return fail(ctx, APX_EINVAL, "rings, csp_avg and w_min are required");
+  AvgArgs a;
+  a.n_avg = st->n_avg;
+  a.slot = (int)(st->samples % st->n_avg);
+  a.m = st->samples + 1 < st->n_avg ? (int)st->samples + 1 : st->n_avg;
+  a.first = st->samples == 0 ? 1 : 0;
+  a.dw_min = st->dw_min;
+  a.csp_ring = st->csp_ring;
+  a.w_ring = st->w_ring;
+  a.csp_avg = csp_avg;
+  a.w_min = w_min;
+  a.w_avg = w_avg;
+  apx_status s = precision_impl(ctx, atoms, nl, p, w0_extra, csp, w0, w, mask, active, n_active, &a);
+  if (s == APX_OK) st->samples += 1;
+  return s;
 }

@@ -190,6 +190,44 @@ def compute_precision(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params
     return out
 
 
+class TimeAveragedSwitch:
+    """State of apx_compute_precision_avg: the CSP and spread-weight rings [n_avg][n], the
+    sample counter and the filtered weight w (kept between calls)."""
+
+    def __init__(self, n: int, n_avg: int, dw_min: float, device="cuda"):
+        self.n, self.n_avg, self.dw_min = int(n), int(n_avg), float(dw_min)
+        self.csp_ring = torch.zeros((self.n_avg, self.n), dtype=torch.float64, device=device)
+        self.w_ring = torch.zeros((self.n_avg, self.n), dtype=torch.float64, device=device)
+        self.w = torch.zeros(self.n, dtype=torch.float64, device=device)
+        self.samples = 0
+
+    def update(self, ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w0_extra=None,
+               csp=None) -> dict:
+        """One sample at the positions of ``atoms``; ``csp`` given skips the CSP pass."""
+        ctx.bind_stream()
+        n = atoms.n
+        if n != self.n:
+            raise ValueError("atom count differs from the state's")
+        dev = atoms.pos.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = dict(csp=csp if csp is not None else torch.empty(n, **f64), csp_avg=torch.empty(n, **f64),
+                   w0=torch.empty(n, **f64), w_min=torch.empty(n, **f64), w_avg=torch.empty(n, **f64),
+                   mask=torch.empty(n, dtype=torch.uint8, device=dev),
+                   active=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+        st = B.AvgState(self.n_avg, 0, self.samples, self.dw_min, self.csp_ring.data_ptr(), self.w_ring.data_ptr())
+        na = C.c_int64(0)
+        a, s, pp = atoms.struct(), nl.struct(), prec_struct(params, csp is not None)
+        ctx._check(ctx.lib.apx_compute_precision_avg(ctx.h, C.byref(a), C.byref(s), C.byref(pp), C.byref(st),
+                                                     _p(w0_extra), _p(out["csp"]), _p(out["csp_avg"]),
+                                                     _p(out["w0"]), _p(out["w_min"]), _p(out["w_avg"]),
+                                                     _p(self.w), _p(out["mask"]), _p(out["active"]), C.byref(na)))
+        self.samples = int(st.samples)
+        out["w"] = self.w.clone()
+        out["n_active"] = int(na.value)
+        out["active"] = out["active"][: out["n_active"]]
+        return out
+
+
 def eam_forces(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, params, w=None) -> dict:
     ctx.bind_stream()
     n = atoms.n
@@ -302,10 +340,11 @@ class MD:
 
     def __init__(self, ctx: Context, atoms: DeviceAtoms, eam, ace: AceModel | None, prec, *, dt=1e-3,
                  mass=63.546, skin=0.5, max_nb=80, precision_every=10, ace_precision="fp32",
-                 mode="adaptive", indenter=None):
+                 mode="adaptive", indenter=None, avg_samples=0, avg_dw_min=0.0):
         self.ctx = ctx
         self.atoms = atoms
         p = B.MdParams()
+        p.avg_samples, p.avg_dw_min = int(avg_samples), float(avg_dw_min)
         p.dt, p.mass, p.skin, p.max_nb = float(dt), float(mass), float(skin), int(max_nb)
         p.precision_every = int(precision_every)
         p.ace_precision = B.APX_FP32 if ace_precision == "fp32" else B.APX_FP64
