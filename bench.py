@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--full-steps", type=int, default=None, help="timed full-ACE steps (default: --steps)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-full", action="store_true", help="skip the full-ACE comparison")
+    ap.add_argument("--no-avg", action="store_true", help="skip the time-averaged-weights run")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the adaptive timed region (for external profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -56,7 +57,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_models(stats, n, n_act, nb_avg, nb_act_avg):
+def kernel_models(stats, n, n_act, nb_avg, nb_act_avg, avg_samples=1):
     """Algorithmic work per launch of each kernel: (bound, amount, unit).
 
     HBM kernels count the bytes a kernel must move (each array element once, the
@@ -86,6 +87,11 @@ def kernel_models(stats, n, n_act, nb_avg, nb_act_avg):
         "md.kick_drift": ("hbm", n * (24 * 4 + 24), "byte"),
         "md.kick": ("hbm", n * 72, "byte"),
         "blend": ("hbm", n * (8 * 3 + 48 + 8 + 24), "byte"),
+        # time-averaged weights with full rings of m samples: the sample in and to the ring,
+        # the m - 1 older samples, the outputs (CSP mean, w0, spread seed; filtered weight,
+        # mask, compaction flag), the frozen mask / the previous weight
+        "prec.avg_csp": ("hbm", n * (8 * (avg_samples + 4) + 1), "byte"),
+        "prec.avg_w": ("hbm", n * (8 * (avg_samples + 2) + 5), "byte"),
     }
 
 
@@ -259,9 +265,9 @@ def main():
     stats = model.stats()
     vel0 = torch.as_tensor(s.vel, dtype=torch.float64, device="cuda").contiguous()
 
-    def run(mode, steps, warm, profile):
+    def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0):
         md = ops.MD(ctx, atoms, eam_p, model, prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
-                    ace_precision="fp32", mode=mode, indenter=ind)
+                    ace_precision="fp32", mode=mode, indenter=ind, avg_samples=avg_samples, avg_dw_min=avg_dw_min)
         pos = atoms.pos.clone()
         vel = vel0.clone()
         f, w = md.init(pos)
@@ -329,6 +335,26 @@ def main():
         "atoms": int(wmask.sum().item())}
     del nl, a64, a32, d, dd
     torch.cuda.empty_cache()
+
+    if not args.no_avg:
+        # the paper's time-averaged switching: a 110-fs window, here 11 samples at one
+        # weight update per 10 steps, minimum step 1/11; warm-up until the rings are full
+        na, wa = 11, 10 * 11
+        log(f"time-averaged weights ({na} samples): {wa} warm-up + {K} timed steps")
+        dt_t, st_t, prof_t, tim_t = run("adaptive", K, wa, True, avg_samples=na, avg_dw_min=1.0 / na)
+        models_t = kernel_models(stats, n, st_t["ace_atoms"] / K, nb_avg, 42.0, avg_samples=na)
+        result["time_averaged"] = {
+            "avg_samples": na, "window_fs": 10 * na, "dw_min": 1.0 / na, "warmup": wa,
+            "atom_steps_per_s": n * K / dt_t, "ms_per_step": dt_t / K * 1e3,
+            "active_atoms": int(st_t["n_active"]), "active_atoms_mean": st_t["ace_atoms"] / K,
+            "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
+                                          [t / K for t in tim_t])),
+            "kernels": {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
+                        for k, v in prof_t.items() if k.startswith("prec.")},
+            "roofline": {k: roofline_for(k, models_t[k], *prof_t[k]) for k in ("prec.avg_csp", "prec.avg_w")
+                         if k in prof_t},
+        }
+        log(f"time-averaged {dt_t / K * 1e3:.3f} ms/step, active mean {st_t['ace_atoms'] / K:.0f}")
 
     if not args.no_full:
         log(f"full ACE: 1 warm-up + {KF} timed steps")

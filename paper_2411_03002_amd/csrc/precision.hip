@@ -387,7 +387,7 @@ apx_status precision_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist*
     APX_LAUNCH_CHECK(ctx);
   }
   if (avg) {
-    ProfScope ps(ctx, "prec.avg");
+    ProfScope ps(ctx, "prec.avg_csp");
     k_avg_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, avg->csp_ring,
                                                            avg->slot, avg->n_avg, avg->m, avg->csp_avg, w0, ws);
     APX_LAUNCH_CHECK(ctx);
@@ -421,14 +421,18 @@ apx_status precision_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist*
   }
   APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
   APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
-  ProfScope ps(ctx, "prec.compact");
-  if (avg)
+  if (avg) {
+    ProfScope ps(ctx, "prec.avg_w");
     k_avg_w<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ws, avg->w_ring, avg->slot, avg->n_avg, avg->m,
                                                          avg->first, avg->dw_min, avg->w_avg, w, mask,
                                                          ctx->itmp.as<int>());
-  else
+    APX_LAUNCH_CHECK(ctx);
+  }
+  ProfScope ps(ctx, "prec.compact");
+  if (!avg) {
     k_mask<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, mask, ctx->itmp.as<int>());
-  APX_LAUNCH_CHECK(ctx);
+    APX_LAUNCH_CHECK(ctx);
+  }
   s = scan_exclusive(ctx, ctx->itmp.as<int>(), n, ctx->itmp2.as<int>());
   if (s != APX_OK) return s;
   k_compact<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->itmp.as<int>(), ctx->itmp2.as<int>(), active);

@@ -190,3 +190,59 @@ def test_void_run_nve_frozen_weights(ops_ctx):
     print(f"detected {st['n_active']}, energy spread {drift:.3e} eV/atom", flush=True)
     assert st["n_active"] > 0
     assert drift < 3e-5
+
+
+def test_indentation_block_time_averaged_weights(ops_ctx):
+    """Time-averaged switching on the 4,000,000-atom block over five samples (ring of three,
+    minimum step 0.05), each at fresh thermal displacements of the mobile atoms.  Every
+    atom: the means, the switch, the filter and the mask against their definitions applied
+    to the library's own sample fields; sampled atoms: the CSP sample against the oracle
+    on a cut cluster, and the spread weight against its definition over the library's
+    averaged w0 field."""
+    ops, ctx = ops_ctx
+    print("\n[case] full size: 100^3-cell indentation block, time-averaged weights", flush=True)
+    from oracle import averaging
+    s = configs.cfg2()
+    prec = synth.precision_hyb1()
+    n_avg, dw = 3, 0.05
+    dev = ops.TimeAveragedSwitch(s.n, n_avg, dw)
+    base = s.pos.copy()
+    mob = ~s.frozen.astype(bool)
+    rng = np.random.default_rng(21)
+    csp_h, wmin_h, w_prev = [], [], None
+    for k in range(5):
+        d = rng.normal(0.0, 0.05, size=base.shape)
+        d[:, ~mob] = 0.0
+        s.pos = synth.wrap_positions(base + d, s.lo, s.hi, s.periodic)
+        atoms = ops.device_atoms(s)
+        nl = ops.build_neighbors(ctx, atoms, 5.5, max_nb=MAX_NB)
+        out = dev.update(ctx, atoms, nl, prec)
+        o = {key: out[key].cpu().numpy() for key in ("csp", "csp_avg", "w0", "w_min", "w_avg", "w", "mask", "active")}
+        csp_h = ([o["csp"]] + csp_h)[:n_avg]
+        wmin_h = ([o["w_min"]] + wmin_h)[:n_avg]
+        ca = averaging.moving_average(csp_h)
+        assert np.all((o["csp_avg"] == ca) | (np.isinf(o["csp_avg"]) & np.isinf(ca)))
+        w0 = precision.w0_from_csp(ca, prec.csp_lo, prec.csp_hi, prec.switch_kind, s.frozen)
+        assert np.array_equal(o["w0"], w0)
+        assert np.array_equal(o["w_avg"], averaging.moving_average(wmin_h))
+        w_prev = averaging.min_step_filter(o["w_avg"], w_prev, dw)
+        assert np.array_equal(o["w"], w_prev)
+        assert np.array_equal(o["mask"], (w_prev > 0).astype(np.uint8))
+        assert np.array_equal(o["active"], np.nonzero(w_prev > 0)[0])
+        # sampled atoms: CSP at these positions, spread weight over the averaged w0 field
+        cut = Cutter(s)
+        det = np.nonzero((o["w0"] > 0) & mob)[0]
+        smp = np.concatenate([rng.choice(np.nonzero(mob)[0], 4, replace=False), rng.choice(det, min(3, det.size),
+                                                                                            replace=False)])
+        for i in smp:
+            cl, idx, c = cut.cluster(i, R_CLUSTER)
+            csr = geometry.neighbor_csr(cl.pos, cl.lo, cl.hi, cl.periodic, 5.5)
+            c_ref = precision.csp(cl.pos, cl.lo, cl.hi, cl.periodic, csr, frozen=cl.frozen)[c]
+            assert o["csp"][i] == c_ref or (np.isinf(o["csp"][i]) and np.isinf(c_ref)), (k, i)
+            big, bidx, bc = cut.cluster(i, prec.r_hi + 0.5)
+            w_ref = precision.spread(big.pos, big.lo, big.hi, big.periodic, o["w0"][bidx], prec.r_lo, prec.r_hi,
+                                     big.frozen)[bc]
+            assert o["w_min"][i] == w_ref, (k, i)
+        print(f"sample {k}: detected {int(o['mask'].sum())}, held by the minimum step "
+              f"{int(np.sum(o['w'] != o['w_avg']))}", flush=True)
+    torch.cuda.empty_cache()
