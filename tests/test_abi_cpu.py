@@ -43,7 +43,8 @@ def test_basis_size_without_device():
 def test_struct_layouts_match_c(tmp_path):
     structs = {"apx_atoms": binding.Atoms, "apx_nlist": binding.NList, "apx_prec_params": binding.PrecParams,
                "apx_eam_params": binding.EamParams, "apx_ace_desc": binding.AceDesc,
-               "apx_md_params": binding.MdParams, "apx_md_stats": binding.MdStats}
+               "apx_md_params": binding.MdParams, "apx_md_stats": binding.MdStats,
+               "apx_avg_state": binding.AvgState}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "apx.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
