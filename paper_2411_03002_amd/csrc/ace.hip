@@ -310,43 +310,54 @@ __device__ __forceinline__ void pair_fwd(const T* __restrict__ As, const int* re
 // radial index (coefficient loads of a segment issued together).  The pair's terms c.B
 // (at most (l_max + 1) n_max of them) are summed by fused multiply-adds, and the pair's
 // two partial sums enter the running sums with compensation.
-template <class T, int LMAX, int NMAX, int TILE, bool COMP, int L1, int L2>
-__device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
-                                           int n_max, Acc<T>& acc) {
-  using C = Couple<LMAX, L1, L2>;
-  constexpr int P2 = (LMAX + 1) * (LMAX + 1);
-  constexpr int ST = TILE + 1;
-  const int o1 = rec[0], o2 = rec[1];
-  T a[2 * L1 + 1], bb[2 * L2 + 1], P[P2];
-#pragma unroll
-  for (int m = 0; m < 2 * L1 + 1; ++m) a[m] = As[(o1 + m) * ST + t];
-#pragma unroll
-  for (int m = 0; m < 2 * L2 + 1; ++m) bb[m] = As[(o2 + m) * ST + t];
-#pragma unroll
-  for (int m = 0; m < P2; ++m) P[m] = T(0);
-  C::template fwd<T>(a, bb, P);
-  T p1 = T(0), p2 = T(0);
-#pragma unroll
-  for (int L = 0; L <= LMAX; ++L) {
-    if ((C::kMask >> L) & 1) {
-      const int q0 = __builtin_amdgcn_readfirstlane(rec[4 + L]);
-      const int q1 = __builtin_amdgcn_readfirstlane(rec[5 + L]);
+// The pair's third blocks of degree L: P_LM by the per-degree coupling, then B = P.A_n3L
+// for the pair's run of n3 (wave-uniform bounds; the loop is unrolled over NMAX).
+template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
+__device__ __forceinline__ void pair_fwd_deg(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
+                                             const T* a, const T* bb, T& p1, T& p2) {
+  if constexpr ((L1 + L2 + L) % 2 == 0 && L >= (L1 > L2 ? L1 - L2 : L2 - L1) && L <= L1 + L2 && L <= LMAX) {
+    constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+    constexpr int ST = TILE + 1;
+    const int q0 = __builtin_amdgcn_readfirstlane(rec[4 + L]);
+    const int q1 = __builtin_amdgcn_readfirstlane(rec[5 + L]);
+    if (q0 < q1) {
       const int n30 = __builtin_amdgcn_readfirstlane((rec[10 + L] - L * L) / P2);
-      if (q0 < q1) {
+      const int n3e = n30 + (q1 - q0);
+      T P[2 * L + 1];
 #pragma unroll
-        for (int n3 = 0; n3 < NMAX; ++n3) {
-          if (n3 >= n30 && n3 < n_max) {
-            const Coef2<T> c = tb.tc[q0 + n3 - n30];
-            T B = T(0);
+      for (int m = 0; m < 2 * L + 1; ++m) P[m] = T(0);
+      Couple3<LMAX, L1, L2, L>::template fwd<T>(a, bb, P);
 #pragma unroll
-            for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[L * L + mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
-            p1 = fma(c.c1, B, p1);
-            p2 = fma(c.c2, B, p2);
-          }
+      for (int n3 = 0; n3 < NMAX; ++n3) {
+        if (n3 >= n30 && n3 < n3e) {
+          const Coef2<T> c = tb.tc[q0 + n3 - n30];
+          T B = T(0);
+#pragma unroll
+          for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
+          p1 = fma(c.c1, B, p1);
+          p2 = fma(c.c2, B, p2);
         }
       }
     }
   }
+}
+
+template <class T, int LMAX, int NMAX, int TILE, bool COMP, int L1, int L2>
+__device__ __forceinline__ void pair_fwd_n(const T* __restrict__ As, const int* rec, const AceTables<T>& tb, int t,
+                                           int n_max, Acc<T>& acc) {
+  constexpr int ST = TILE + 1;
+  const int o1 = rec[0], o2 = rec[1];
+  T a[2 * L1 + 1], bb[2 * L2 + 1];
+#pragma unroll
+  for (int m = 0; m < 2 * L1 + 1; ++m) a[m] = As[(o1 + m) * ST + t];
+#pragma unroll
+  for (int m = 0; m < 2 * L2 + 1; ++m) bb[m] = As[(o2 + m) * ST + t];
+  T p1 = T(0), p2 = T(0);
+  pair_fwd_deg<T, LMAX, NMAX, TILE, L1, L2, 0>(As, rec, tb, t, a, bb, p1, p2);
+  pair_fwd_deg<T, LMAX, NMAX, TILE, L1, L2, 1>(As, rec, tb, t, a, bb, p1, p2);
+  pair_fwd_deg<T, LMAX, NMAX, TILE, L1, L2, 2>(As, rec, tb, t, a, bb, p1, p2);
+  pair_fwd_deg<T, LMAX, NMAX, TILE, L1, L2, 3>(As, rec, tb, t, a, bb, p1, p2);
+  pair_fwd_deg<T, LMAX, NMAX, TILE, L1, L2, 4>(As, rec, tb, t, a, bb, p1, p2);
   acc_sum<T, COMP>(acc.s1, acc.e1, p1);
   acc_sum<T, COMP>(acc.s2, acc.e2, p2);
 }
@@ -836,8 +847,8 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
     C::template fwd<T>(a, b, P);
 #pragma unroll
     for (int n3 = 0; n3 < NMAX; ++n3) {
-      // the stream's coefficients are zero outside [n30, n_max) and so is A3 beyond
-      // n_max: those terms add exact zeros, which costs less than branching on them
+      // the stream's coefficients are zero outside the pair's run of n3 and A3 is zero
+      // beyond n_max: those terms add exact zeros, which costs less than branching on them
       {
         const T d = fma(fp, cld(Ec + kAdjC2 + n3), cld(Ec + kAdjC1 + n3));
 #pragma unroll

@@ -31,6 +31,9 @@ constexpr int kUnitRec = 8;
 // where there is no triple), so that a pair costs one batch of independent scalar loads.
 constexpr int kAdjRec = 32;
 constexpr int kAdjC1 = 8, kAdjC2 = 20;
+// host copy of a stream entry: off1, off2, run label, other label, first n3, first triple,
+// number of triples
+constexpr int kAdjEnt = 7;
 
 template <class T>
 struct alignas(2 * sizeof(T)) Coef2 {
@@ -77,6 +80,6 @@ struct apx_ace_model {
   apx::AceTables<float> t32{};
   std::vector<double> W;      // host copy [l][n][k]
   std::vector<int> t_v, b1_v, b2_v;  // basis index of every coefficient slot (host)
-  std::vector<int> adj_ent;          // adjoint stream entries: off1, off2, run, other, n30, first triple
+  std::vector<int> adj_ent;          // adjoint stream entries, kAdjEnt ints each
   apx::DevBuf adj;                   // adjoint pair stream (kAdjRec words per entry)
 };

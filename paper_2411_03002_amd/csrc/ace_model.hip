@@ -3,8 +3,10 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
-#include <tuple>
 #include <cstring>
+#include <map>
+#include <tuple>
+#include <utility>
 
 #include "ace_coupling_gen.h"
 #include "ace_model.h"
@@ -35,6 +37,37 @@ int terms_of(int l1, int l2) {
 
 bool coupled(int l1, int l2, int l3) { return ((l1 + l2 + l3) % 2 == 0) && l3 >= std::abs(l1 - l2) && l3 <= l1 + l2; }
 
+// Coupling terms of (l1, l2) -> L alone (the per-degree functions Couple3).
+template <int LMAX, int L1, int L2, int L>
+constexpr int terms3() {
+  if constexpr ((L1 + L2 + L) % 2 == 0 && L >= (L1 > L2 ? L1 - L2 : L2 - L1) && L <= L1 + L2 && L <= LMAX)
+    return Couple3<LMAX, L1, L2, L>::kTerms;
+  else
+    return 0;
+}
+template <int LMAX, int L1, int L2, int... Ls>
+int terms3_L(int L, std::integer_sequence<int, Ls...>) {
+  int r = 0;
+  ((r = (L == Ls ? terms3<LMAX, L1, L2, Ls>() : r)), ...);
+  return r;
+}
+template <int LMAX, int L1, int... L2s>
+int terms3_l2(int l2, int L, std::integer_sequence<int, L2s...>) {
+  int r = 0;
+  ((r = (l2 == L2s ? terms3_L<LMAX, L1, L2s>(L, std::make_integer_sequence<int, LMAX + 1>{}) : r)), ...);
+  return r;
+}
+template <int LMAX, int... L1s>
+int terms3_l1(int l1, int l2, int L, std::integer_sequence<int, L1s...>) {
+  int r = 0;
+  ((r = (l1 == L1s ? terms3_l2<LMAX, L1s>(l2, L, std::make_integer_sequence<int, LMAX + 1>{}) : r)), ...);
+  return r;
+}
+int terms3_of(int l_max, int l1, int l2, int L) {
+  return l_max == 4 ? terms3_l1<4>(l1, l2, L, std::make_integer_sequence<int, 5>{})
+                    : terms3_l1<3>(l1, l2, L, std::make_integer_sequence<int, 4>{});
+}
+
 struct Catalogue {
   long long n_basis = 0;
   std::vector<int> pairs, t_v, b1_off, b1_v, b2_off, b2_v, units, wave_units, adj_ent;
@@ -61,50 +94,65 @@ Catalogue build_catalogue(int n_max, int l_max) {
         c.b2_off.push_back(l);
         c.b2_v.push_back((int)v++);
       }
-  // B3: enumerate in catalogue order to assign basis indices, then regroup per pair by L
+  // B3: the basis indices follow the enumeration p1 <= p2 <= p3 of labels p = n (l_max+1) + l
+  // (the basis definition).  The real Gaunt product of three blocks is symmetric in them,
+  // so each triple may be evaluated as any of its labels coupled to the pair of the other
+  // two.  Here the third block is the label that comes first in degree-major order
+  // (l, then n) and the pair holds the other two: a pair (q2 <= q3) then meets third
+  // blocks of degree L < l(q2) for every n, and of degree l(q2) for n <= n(q2).  Each pair
+  // and degree thus has a run of third blocks n = 0, 1, ... of full or near-full length,
+  // which makes fewer (pair, degree) combinations than the enumeration order would.
   struct PairTmp {
     int rec[kPairRec];
     std::vector<int> v;  // basis indices of its triples, in segment order
     double cost;
   };
-  std::vector<PairTmp> tmp;
+  auto lkey = [LL](int p) { return std::make_pair(p % LL, p / LL); };
+  std::map<std::pair<int, int>, std::vector<std::vector<std::pair<int, int>>>> groups;  // (n3, v) by L
   for (int p1 = 0; p1 < P; ++p1)
-    for (int p2 = p1; p2 < P; ++p2) {
-      const int l1 = p1 % LL, l2 = p2 % LL;
-      std::vector<std::vector<std::pair<int, int>>> byL(LL);  // (off3, v)
-      int found = 0;
+    for (int p2 = p1; p2 < P; ++p2)
       for (int p3 = p2; p3 < P; ++p3) {
-        const int l3 = p3 % LL;
-        if (!coupled(l1, l2, l3)) continue;
-        byL[l3].push_back({off(p3), (int)v++});
-        ++found;
+        if (!coupled(p1 % LL, p2 % LL, p3 % LL)) continue;
+        std::array<int, 3> s3 = {p1, p2, p3};
+        std::sort(s3.begin(), s3.end(), [&](int a, int b) { return lkey(a) < lkey(b); });
+        auto& g = groups[{s3[1], s3[2]}];
+        if (g.empty()) g.resize(LL);
+        g[s3[0] % LL].push_back({s3[0] / LL, (int)v++});
       }
-      if (!found) continue;
-      PairTmp pt{};
-      pt.rec[0] = off(p1);
-      pt.rec[1] = off(p2);
-      pt.rec[2] = l1 * LL + l2;
-      pt.rec[3] = p1 / LL;
-      pt.rec[15] = p2 / LL;
-      const int nterm = l_max == 4 ? terms_of<4>(l1, l2) : terms_of<3>(l1, l2);
-      c.coupling_terms += nterm;
-      pt.cost = 8.0 + nterm;
-      int t = 0;
-      for (int L = 0; L < LL; ++L) {
-        pt.rec[4 + L] = t;
-        pt.rec[10 + L] = byL[L].empty() ? 0 : byL[L][0].first;
-        for (size_t e = 0; e < byL[L].size(); ++e) {
-          // third blocks of one degree are consecutive in n: offsets step by (l_max+1)^2
-          if (byL[L][e].first != pt.rec[10 + L] + (int)e * LL * LL) throw 1;
-          pt.v.push_back(byL[L][e].second);
-          pt.cost += 2 * L + 1 + 2;
-          c.triple_width += 2 * L + 1;
-          ++t;
-        }
+  std::vector<PairTmp> tmp;
+  for (auto& kv : groups) {
+    const int q2 = kv.first.first, q3 = kv.first.second;
+    const int l1 = q2 % LL, l2 = q3 % LL;
+    auto& byL = kv.second;
+    PairTmp pt{};
+    pt.rec[0] = off(q2);
+    pt.rec[1] = off(q3);
+    pt.rec[2] = l1 * LL + l2;
+    pt.rec[3] = q2 / LL;
+    pt.rec[15] = q3 / LL;
+    pt.cost = 8.0;
+    int t = 0;
+    for (int L = 0; L < LL; ++L) {
+      std::sort(byL[L].begin(), byL[L].end());
+      pt.rec[4 + L] = t;
+      pt.rec[10 + L] = byL[L].empty() ? 0 : byL[L][0].first * LL * LL + L * L;
+      if (!byL[L].empty()) {
+        const int nterm = terms3_of(l_max, l1, l2, L);
+        c.coupling_terms += nterm;
+        pt.cost += nterm;
       }
-      for (int L = LL; L <= 5; ++L) pt.rec[4 + L] = t;
-      tmp.push_back(pt);
+      for (size_t e = 0; e < byL[L].size(); ++e) {
+        // third blocks of one degree are consecutive in n: offsets step by (l_max+1)^2
+        if (byL[L][e].first != byL[L][0].first + (int)e) throw 1;
+        pt.v.push_back(byL[L][e].second);
+        pt.cost += 2 * L + 1 + 2;
+        c.triple_width += 2 * L + 1;
+        ++t;
+      }
     }
+    for (int L = LL; L <= 5; ++L) pt.rec[4 + L] = t;
+    tmp.push_back(pt);
+  }
   c.n_basis = v;
   // group the pairs by coupling type so that a wave stays in one specialisation for
   // long runs of pairs (instruction-cache locality); within a type order them by the
@@ -171,7 +219,7 @@ Catalogue build_catalogue(int n_max, int l_max) {
     if (u[1] < 0) continue;
     const int L = u[1], type = u[0];
     const int l1 = type / LL, l2 = type % LL;
-    u[5] = (int)(c.adj_ent.size() / 6);
+    u[5] = (int)(c.adj_ent.size() / kAdjEnt);
     for (int k = u[2]; k < u[3]; ++k) {
       const int* r = tmp[k].rec;
       if (r[5 + L] <= r[4 + L]) continue;
@@ -179,9 +227,9 @@ Catalogue build_catalogue(int n_max, int l_max) {
       const int noth = l1 >= l2 ? r[15] : r[3];
       if ((noth < half_n) != (u[4] == 0)) continue;
       const int n30 = (r[10 + L] - L * L) / (LL * LL);
-      c.adj_ent.insert(c.adj_ent.end(), {r[0], r[1], nrun, noth, n30, r[4 + L]});
+      c.adj_ent.insert(c.adj_ent.end(), {r[0], r[1], nrun, noth, n30, r[4 + L], r[5 + L] - r[4 + L]});
     }
-    u[6] = (int)(c.adj_ent.size() / 6);
+    u[6] = (int)(c.adj_ent.size() / kAdjEnt);
   }
   // each launch group is dealt to the waves separately, longest processing time first
   for (auto& u : units) c.units.insert(c.units.end(), u.begin(), u.end());
@@ -263,14 +311,14 @@ static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalo
 // The adjoint pair stream with the coefficients of the current model (kAdjRec words per
 // entry; coefficients as float32).
 static std::vector<int32_t> adjoint_stream(const apx_ace_model* m, const double* c1, const double* c2) {
-  const size_t ne = m->adj_ent.size() / 6;
+  const size_t ne = m->adj_ent.size() / kAdjEnt;
   std::vector<int32_t> out(ne * kAdjRec, 0);
   for (size_t e = 0; e < ne; ++e) {
-    const int* a = m->adj_ent.data() + 6 * e;
+    const int* a = m->adj_ent.data() + kAdjEnt * e;
     int32_t* o = out.data() + e * kAdjRec;
     for (int k = 0; k < 5; ++k) o[k] = a[k];
-    const int n30 = a[4], q0 = a[5];
-    for (int n3 = n30; n3 < m->n_max; ++n3) {
+    const int n30 = a[4], q0 = a[5], nt = a[6];
+    for (int n3 = n30; n3 < n30 + nt; ++n3) {
       const int v = m->t_v[q0 + n3 - n30];
       const float f1 = (float)c1[v], f2 = (float)c2[v];
       std::memcpy(o + kAdjC1 + n3, &f1, 4);
