@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
 //   accR[m]      the adjoint of the pair label with the larger degree, accumulated over
 //                the run of pairs sharing it (pairs are sorted by it)
 //   accO[h][m]   the adjoint of the other pair label (one of at most (NMAX + 1)/2 values
-//                in the unit's half)
+//                in the unit's range of other labels)
 // and adds them to the tile's adjoint in global memory with float atomics when a run or
 // the unit ends.
 // Every lane adds, padded lanes (beyond the last active atom) included: their slots lie
@@ -788,11 +788,11 @@ __device__ __forceinline__ void third_flush(T* __restrict__ Abt, int n_max, int 
   }
 }
 
-// The pairs of one unit (l1, l2, L) for one half of the other label; the third-block
+// The pairs of one unit (l1, l2, L) for a range of the other label; the third-block
 // registers A3 and their adjoint acc3 are the caller's (shared by the units of one degree).
 template <class T, int LMAX, int NMAX, int TILE, int L1, int L2, int L>
 __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict__ Abt, const AceTables<T>& tb,
-                                         int eb, int ee, int half, int n_max, int t, T fp,
+                                         int eb, int ee, int obase, int oend, int t, T fp,
                                          const T (&A3)[NMAX][2 * L + 1], T (&acc3)[NMAX][2 * L + 1]) {
   using C = Couple3<LMAX, L1, L2, L>;
   constexpr int ST = TILE + 1;
@@ -804,13 +804,11 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   constexpr int LR = RUN1 ? L1 : L2;
   constexpr int LO = RUN1 ? L2 : L1;
   static_assert(NMAX <= kAdjC2 - kAdjC1, "the pair stream holds coefficients for n3 < 12");
-  // this unit covers the pairs whose smaller-degree label lies in one half of [0, n_max)
-  const int hn = (n_max + 1) / 2;
-  const int obase = half ? hn : 0;
-  const int oend = half ? n_max : hn;
-  constexpr int NH = (NMAX + 1) / 2;  // labels in a half, at most
+  // this unit covers the pairs whose other label lies in [obase, oend), at most
+  // (n_max + 1)/2 labels
+  constexpr int NH = (NMAX + 1) / 2;
   T accR[NR];
-  T accO[NH][NO];  // adjoint of the other label, by its position in the half
+  T accO[NH][NO];  // adjoint of the other label, by its position in the range
 #pragma unroll
   for (int h = 0; h < NH; ++h) {
 #pragma unroll
@@ -1037,9 +1035,10 @@ __global__ void __launch_bounds__(NW * 64, G <= 2 ? 2 : 1) k_ace_adjoint(const T
     const int type = cld(ur);
     const int L = cld(ur + 1);
     const int pb = cld(ur + 2);
-    const int half = cld(ur + 4);
+    const int obase = cld(ur + 4);
     const int eb = cld(ur + 5);
     const int ee = cld(ur + 6);
+    const int oend = cld(ur + 7);
     if (L < 0) {
       if constexpr (G == 0) low_order_unit<T, LMAX, TILE>(As, Abt, tb, nb1, n_max, pb, t, fp);
       continue;
@@ -1050,7 +1049,7 @@ __global__ void __launch_bounds__(NW * 64, G <= 2 ? 2 : 1) k_ace_adjoint(const T
 #define APX_UNIT(A_, B_, C_)                                                                              \
   case (A_ * (LMAX + 1) + B_) * (LMAX + 1) + C_:                                                          \
     if constexpr (C_ == LG)                                                                               \
-      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, half, n_max, t, fp, A3, acc3);       \
+      unit_bwd<T, LMAX, NMAX, TILE, A_, B_, C_>(As, Abt, tb, eb, ee, obase, oend, t, fp, A3, acc3);       \
     break;
     if constexpr (LMAX == 3) {
       switch (key) { APX_UNIT_CASES_3(APX_UNIT) default: break; }

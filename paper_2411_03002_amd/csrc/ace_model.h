@@ -21,8 +21,9 @@ constexpr int kUnitWaves = 4;
 constexpr int kUnitGroups = 5;
 __host__ __device__ constexpr int unit_group(int L) { return L < 0 ? 0 : L; }
 // ints per adjoint unit record: type, L (-1: a B1/B2 unit), first pair (B1/B2: the label
-// n1), end pair, half (0: the other pair label n < (n_max + 1)/2, 1: the rest), first and
-// end entry of the unit's pair stream, padding.
+// n1), end pair, first other label, first and end entry of the unit's pair stream, end
+// other label (the unit holds the pairs whose other label lies in [first, end), a range
+// of at most (n_max + 1)/2 labels).
 constexpr int kUnitRec = 8;
 // Words per entry of the adjoint pair stream (float32 path): one entry per pair of a unit
 // that has third blocks of the unit's degree in the unit's half, holding

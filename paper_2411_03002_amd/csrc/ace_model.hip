@@ -177,9 +177,22 @@ Catalogue build_catalogue(int n_max, int l_max) {
   // adjoint units (type, L) over the contiguous pair range of each type, plus the B1/B2
   // units, dealt to the waves by longest processing time first
   std::vector<std::array<int, kUnitRec>> units;
-  const int half_n = (n_max + 1) / 2;
+  const int half_n = (n_max + 1) / 2;  // widest range of other labels a unit may hold
   std::vector<double> ucost;
   {
+    // a unit (type, L) covers the pairs whose other label lies in [obase, oend); the
+    // ranges are cut by cost so that every launch group has at least two units per wave
+    int ntypes[kUnitGroups] = {};
+    for (size_t q = 0; q < tmp.size(); ++q) {
+      if (q > 0 && tmp[q].rec[2] == tmp[q - 1].rec[2]) continue;
+      const int l1 = tmp[q].rec[2] / LL, l2 = tmp[q].rec[2] % LL;
+      for (int L = 0; L < LL; ++L) {
+        bool any = false;
+        for (size_t k = q; k < tmp.size() && tmp[k].rec[2] == tmp[q].rec[2]; ++k)
+          any = any || tmp[k].rec[5 + L] > tmp[k].rec[4 + L];
+        if (any && coupled(l1, l2, L)) ++ntypes[unit_group(L)];
+      }
+    }
     int q = 0;
     const int np = (int)tmp.size();
     while (q < np) {
@@ -189,18 +202,32 @@ Catalogue build_catalogue(int n_max, int l_max) {
       const int l1 = type / LL, l2 = type % LL;
       for (int L = 0; L < LL; ++L) {
         if (!coupled(l1, l2, L)) continue;
-        for (int h = 0; h < 2; ++h) {
+        std::vector<double> cost_o(n_max, 0.0);
+        for (int k = q; k < e; ++k) {
+          const int noth = l1 >= l2 ? tmp[k].rec[15] : tmp[k].rec[3];
+          const int nt = tmp[k].rec[5 + L] - tmp[k].rec[4 + L];
+          if (nt > 0) cost_o[noth] += 40.0 + 6.0 * nt * (2 * L + 1) + 3.0 * (2 * l1 + 1) * (2 * l2 + 1);
+        }
+        double total = 0.0;
+        for (double x : cost_o) total += x;
+        if (total <= 0.0) continue;
+        const int nt_g = std::max(1, ntypes[unit_group(L)]);
+        const int parts = std::max(2, (2 * kUnitWaves + nt_g - 1) / nt_g);
+        int b = 0;
+        double acc = 0.0;
+        int made = 0;
+        for (int o = 0; o < n_max; ++o) {
+          acc += cost_o[o];
+          const bool cut = o == n_max - 1 || o - b + 1 == half_n || acc >= total * (made + 1) / parts;
+          if (!cut) continue;
           double cst = 0.0;
-          for (int k = q; k < e; ++k) {
-            const int noth = l1 >= l2 ? tmp[k].rec[15] : tmp[k].rec[3];
-            if ((noth < half_n) != (h == 0)) continue;
-            const int nt = tmp[k].rec[5 + L] - tmp[k].rec[4 + L];
-            if (nt > 0) cst += 40.0 + 6.0 * nt * (2 * L + 1) + 3.0 * (2 * l1 + 1) * (2 * l2 + 1);
-          }
+          for (int x = b; x <= o; ++x) cst += cost_o[x];
           if (cst > 0.0) {
-            units.push_back({type, L, q, e, h, 0, 0, 0});
+            units.push_back({type, L, q, e, b, 0, 0, o + 1});
             ucost.push_back(cst + 30.0 * n_max * (2 * L + 1));
           }
+          ++made;
+          b = o + 1;
         }
       }
       q = e;
@@ -225,7 +252,7 @@ Catalogue build_catalogue(int n_max, int l_max) {
       if (r[5 + L] <= r[4 + L]) continue;
       const int nrun = l1 >= l2 ? r[3] : r[15];
       const int noth = l1 >= l2 ? r[15] : r[3];
-      if ((noth < half_n) != (u[4] == 0)) continue;
+      if (noth < u[4] || noth >= u[7]) continue;
       const int n30 = (r[10 + L] - L * L) / (LL * LL);
       c.adj_ent.insert(c.adj_ent.end(), {r[0], r[1], nrun, noth, n30, r[4 + L], r[5 + L] - r[4 + L]});
     }
