@@ -776,15 +776,41 @@ __device__ __forceinline__ void third_load(const T* __restrict__ As, int n_max, 
   }
 }
 
-template <class T, int LMAX, int NMAX, int TILE, int L>
-__device__ __forceinline__ void third_flush(T* __restrict__ Abt, int n_max, int t, const T (&acc3)[NMAX][2 * L + 1]) {
+// The block's waves sum their third-block adjoints through LDS (the upper half of the
+// waves hands its sums to the lower half, which stores the partial sums), then every
+// wave adds a share of the elements to global memory: one atomic per element and block.
+// lds holds (NW/2) * NMAX * (2L+1) * 64 values; the caller has finished with it.
+template <class T, int LMAX, int NMAX, int TILE, int NW, int L>
+__device__ __forceinline__ void third_flush(T* __restrict__ Abt, T* lds, int n_max, int t, int wv, int lane,
+                                            T (&acc3)[NMAX][2 * L + 1]) {
   constexpr int P2 = (LMAX + 1) * (LMAX + 1);
+  constexpr int NL = 2 * L + 1, NE = NMAX * NL, H = NW / 2;
+  static_assert(NW % 2 == 0, "waves pair up");
+  __syncthreads();
+  if (wv >= H) {
 #pragma unroll
-  for (int n = 0; n < NMAX; ++n) {
-    if (n < n_max) {
+    for (int n = 0; n < NMAX; ++n)
 #pragma unroll
-      for (int m = 0; m < 2 * L + 1; ++m) gadd<T, TILE>(Abt, n * P2 + L * L + m, t, acc3[n][m]);
-    }
+      for (int m = 0; m < NL; ++m) lds[((wv - H) * NE + n * NL + m) * 64 + lane] = acc3[n][m];
+  }
+  __syncthreads();
+  if (wv < H) {
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n)
+#pragma unroll
+      for (int m = 0; m < NL; ++m) {
+        T* q = &lds[(wv * NE + n * NL + m) * 64 + lane];
+        *q = *q + acc3[n][m];
+      }
+  }
+  __syncthreads();
+  for (int e = wv; e < NE; e += NW) {
+    const int n = e / NL, m = e - n * NL;
+    if (n >= n_max) continue;
+    T s = T(0);
+#pragma unroll
+    for (int h = 0; h < H; ++h) s += lds[(h * NE + e) * 64 + lane];
+    gadd<T, TILE>(Abt, n * P2 + L * L + m, t, s);
   }
 }
 
@@ -1058,7 +1084,7 @@ __global__ void __launch_bounds__(NW * 64, G <= 2 ? 2 : 1) k_ace_adjoint(const T
     }
 #undef APX_UNIT
   }
-  third_flush<T, LMAX, NMAX, TILE, LG>(Abt, n_max, t, acc3);
+  third_flush<T, LMAX, NMAX, TILE, NW, LG>(Abt, As, n_max, t, wv, lane, acc3);
 }
 
 template <class T>
@@ -1156,19 +1182,23 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
       return APX_OK;
     };
-    auto adjoint = [&](auto k0, auto k1, auto k2, auto k3, auto k4) -> apx_status {
+    auto adjoint = [&](int nmax_t, auto k0, auto k1, auto k2, auto k3, auto k4) -> apx_status {
       ProfScope ps(ctx, "ace.adjoint");
       static_assert(kUnitGroups == 5, "one kernel per launch group");
       const void* ks[kUnitGroups] = {(const void*)k0, (const void*)k1, (const void*)k2, (const void*)k3,
                                      (const void*)k4};
       for (int g = 0; g < kUnitGroups; ++g) {
         if (m->group_units[g] == 0) continue;
-        if (ensure_lds(ctx, ks[g], ldsa) != APX_OK) return APX_EDEVICE;
-        if (g == 0) k0<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
-        if (g == 1) k1<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
-        if (g == 2) k2<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
-        if (g == 3) k3<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
-        if (g == 4) k4<<<nblk, NWU * 64, ldsa, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        // the staged tile, or the third-block reduction of the group if larger
+        const size_t red = sizeof(T) * (size_t)(NWU / 2) * nmax_t * (2 * g + 1) * 64;
+        const size_t ldsg = ldsa > red ? ldsa : red;
+        if (ldsg > (size_t)lds_max) return fail(ctx, APX_EINVAL, "ACE adjoint needs %zu bytes of LDS", ldsg);
+        if (ensure_lds(ctx, ks[g], ldsg) != APX_OK) return APX_EDEVICE;
+        if (g == 0) k0<<<nblk, NWU * 64, ldsg, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 1) k1<<<nblk, NWU * 64, ldsg, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 2) k2<<<nblk, NWU * 64, ldsg, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 3) k3<<<nblk, NWU * 64, ldsg, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
+        if (g == 4) k4<<<nblk, NWU * 64, ldsg, ctx->stream>>>(sc.A, sc.Ab, n_act, na, m->n_max, tb, m->nb1, sc.fp);
         APX_LAUNCH_CHECK(ctx);
       }
       return APX_OK;
@@ -1177,7 +1207,7 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
 #define APX_PRODUCTS(LM_, NM_)                                                                          \
   s = energy(k_ace_energy<T, LM_, NM_, TILE, NWE, true>);                                               \
   if (s == APX_OK)                                                                                      \
-    s = adjoint(k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>,     \
+    s = adjoint(NM_, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 0>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 1>, \
                 k_ace_adjoint<T, LM_, NM_, TILE, NWU, 2>, k_ace_adjoint<T, LM_, NM_, TILE, NWU, 3>,     \
                 k_ace_adjoint<T, LM_, NM_, TILE, NWU, 4>);
     if constexpr (LMAX == 3) {
