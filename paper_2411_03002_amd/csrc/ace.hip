@@ -959,14 +959,43 @@ __device__ __forceinline__ void low_order_unit(const T* __restrict__ As, T* __re
   X(4, 4, 2) X(4, 4, 4)
 
 // Stages the tile's atomic base into LDS, [a][TILE + 1] (atom fastest; the padding
-// column keeps the stride odd).
+// column keeps the stride odd).  The tile is one contiguous block of the atom-major
+// global array (the buffer holds whole tiles); float32 tiles are read 16 bytes at a
+// time and transposed on the way, values of atoms beyond n_act are zero.
 template <class T, int TILE>
 __device__ __forceinline__ void stage_tile(const T* __restrict__ Ag, T* As, int q0, int n_act, int na, int nthr) {
   constexpr int ST = TILE + 1;
-  for (int e = threadIdx.x; e < TILE * na; e += nthr) {
-    const int t = e / na, a = e - t * na;
-    const int q = q0 + t;
-    As[a * ST + t] = q < n_act ? Ag[(size_t)q * na + a] : T(0);
+  if constexpr (sizeof(T) == 4) {
+    const T* src = Ag + (size_t)q0 * na;
+    const int total = TILE * na;
+    const int rem = n_act - q0;
+    const int valid = (rem < TILE ? rem : TILE) * na;
+    for (int e4 = threadIdx.x * 4; e4 < total; e4 += nthr * 4) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e4 + 3 < valid) {
+        v = *reinterpret_cast<const float4*>(src + e4);
+      } else {
+        if (e4 < valid) v.x = src[e4];
+        if (e4 + 1 < valid) v.y = src[e4 + 1];
+        if (e4 + 2 < valid) v.z = src[e4 + 2];
+      }
+      int t = e4 / na, a = e4 - t * na;
+      const T vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (e4 + k < total) As[a * ST + t] = vv[k];
+        if (++a == na) {
+          a = 0;
+          ++t;
+        }
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < TILE * na; e += nthr) {
+      const int t = e / na, a = e - t * na;
+      const int q = q0 + t;
+      As[a * ST + t] = q < n_act ? Ag[(size_t)q * na + a] : T(0);
+    }
   }
 }
 
