@@ -629,8 +629,16 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
     const int kk = o / LM, lm = o - kk * LM;
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
+    // the K loads of an output are issued together (unrolled to the largest K)
+    T wv_[kMaxK], av_[kMaxK];
+#pragma unroll
+    for (int nn = 0; nn < kMaxK; ++nn) {
+      wv_[nn] = nn < K ? Wp[((size_t)l * K + nn) * K + kk] : T(0);
+      av_[nn] = nn < K ? Abr[(size_t)(nn * LM + lm) * as] : T(0);
+    }
     T v = T(0);
-    for (int nn = 0; nn < K; ++nn) v += Wp[((size_t)l * K + nn) * K + kk] * Abr[(size_t)(nn * LM + lm) * as];
+#pragma unroll
+    for (int nn = 0; nn < kMaxK; ++nn) v += wv_[nn] * av_[nn];
     Ab2[o] = v;
   }
   __syncthreads();
