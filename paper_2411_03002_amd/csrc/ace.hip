@@ -749,8 +749,8 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
 //   acc3[n3][M]  the adjoint of every third block (n3, L)            (registers)
 //   accR[m]      the adjoint of the pair label with the larger degree, accumulated over
 //                the run of pairs sharing it (pairs are sorted by it)
-//   accO[h][m]   the adjoint of the other pair label (one of at most (NMAX + 1)/2 values
-//                in the unit's range of other labels)
+//   accO[h][m]   the adjoint of the other pair label (one of at most unit_width values in
+//                the unit's range of other labels)
 // and adds them to the tile's adjoint in global memory with float atomics when a run or
 // the unit ends.
 // Every lane adds, padded lanes (beyond the last active atom) included: their slots lie
@@ -839,8 +839,8 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
   constexpr int LO = RUN1 ? L2 : L1;
   static_assert(NMAX <= kAdjC2 - kAdjC1, "the pair stream holds coefficients for n3 < 12");
   // this unit covers the pairs whose other label lies in [obase, oend), at most
-  // (n_max + 1)/2 labels
-  constexpr int NH = (NMAX + 1) / 2;
+  // unit_width(L, n_max) <= NH labels
+  constexpr int NH = unit_width(L, NMAX);
   T accR[NR];
   T accO[NH][NO];  // adjoint of the other label, by its position in the range
 #pragma unroll
@@ -1063,13 +1063,13 @@ __global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag
   }
 }
 
-// Degrees 0..2 run at two waves per SIMD (degree 2 spills a few registers, which costs
-// less than the lost occupancy); degrees 3 and 4 need one wave per SIMD.
+// Degrees 0..3 run at two waves per SIMD (their units hold at most 3 and 2 other labels in
+// degrees 2 and 3); degree 4 needs one wave per SIMD.
 // Adjoint of the product basis for the units of one launch group G: the tile's atomic
 // base is staged again, the embedding slope is read from the energy pass, and every
 // wave runs its units (see unit_bwd), adding to the tile's adjoint in global memory.
 template <class T, int LMAX, int NMAX, int TILE, int NW, int G>
-__global__ void __launch_bounds__(NW * 64, G <= 2 ? 2 : 1) k_ace_adjoint(const T* __restrict__ Ag, T* __restrict__ Abg,
+__global__ void __launch_bounds__(NW * 64, G <= 3 ? 2 : 1) k_ace_adjoint(const T* __restrict__ Ag, T* __restrict__ Abg,
                                                             int n_act, int na, int n_max, AceTables<T> tb, int nb1,
                                                             const T* __restrict__ fp_in) {
   static_assert(NW == kUnitWaves, "the unit tables are dealt to kUnitWaves waves");

@@ -25,6 +25,10 @@ __host__ __device__ constexpr int unit_group(int L) { return L < 0 ? 0 : L; }
 // other label (the unit holds the pairs whose other label lies in [first, end), a range
 // of at most (n_max + 1)/2 labels).
 constexpr int kUnitRec = 8;
+// Widest range of other labels an adjoint unit of launch group g may hold (the unit
+// accumulates their adjoints in registers; narrower ranges leave registers to the larger
+// third blocks of the higher degrees).
+__host__ __device__ constexpr int unit_width(int g, int nmax) { return g >= 3 ? 2 : (g == 2 ? 3 : (nmax + 1) / 2); }
 // Words per entry of the adjoint pair stream (float32 path): one entry per pair of a unit
 // that has third blocks of the unit's degree in the unit's half, holding
 // [0] off1, [1] off2, [2] run label n, [3] other label n, [4] first radial index n3 of the

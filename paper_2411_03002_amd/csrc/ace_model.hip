@@ -177,7 +177,6 @@ Catalogue build_catalogue(int n_max, int l_max) {
   // adjoint units (type, L) over the contiguous pair range of each type, plus the B1/B2
   // units, dealt to the waves by longest processing time first
   std::vector<std::array<int, kUnitRec>> units;
-  const int half_n = (n_max + 1) / 2;  // widest range of other labels a unit may hold
   std::vector<double> ucost;
   {
     // a unit (type, L) covers the pairs whose other label lies in [obase, oend); the
@@ -218,7 +217,8 @@ Catalogue build_catalogue(int n_max, int l_max) {
         int made = 0;
         for (int o = 0; o < n_max; ++o) {
           acc += cost_o[o];
-          const bool cut = o == n_max - 1 || o - b + 1 == half_n || acc >= total * (made + 1) / parts;
+          const bool cut = o == n_max - 1 || o - b + 1 == unit_width(unit_group(L), n_max) ||
+                           acc >= total * (made + 1) / parts;
           if (!cut) continue;
           double cst = 0.0;
           for (int x = b; x <= o; ++x) cst += cost_o[x];
