@@ -72,7 +72,10 @@ def kernel_models(stats, n, n_act, nb_avg, nb_act_avg, avg_samples=1):
     f_products = f_energy + f_adjoint
     K, LM = 10, 25
     f_basis = nb_act_avg * (3 * K + 4 * LM + 2 * K * LM) + 2.0 * K * stats["n_atomic_base"]
-    f_force = 2.0 * K * stats["n_atomic_base"] + nb_act_avg * (4 * K * LM + 12 * LM + 6 * K)
+    # the float32 path back-projects the adjoint in its own tile kernel (2 K flop per
+    # atomic-base value); the force kernel then evaluates the neighbour gradients
+    f_backproject = 2.0 * K * stats["n_atomic_base"]
+    f_force = nb_act_avg * (4 * K * LM + 12 * LM + 6 * K)
     row = 4.0 + 4.0 * nb_avg
     return {
         "ace.products": ("alu_fp32", n_act * f_products, "flop"),
@@ -80,6 +83,7 @@ def kernel_models(stats, n, n_act, nb_avg, nb_act_avg, avg_samples=1):
         "ace.adjoint": ("alu_fp32", n_act * f_adjoint, "flop"),
         "ace.basis": ("alu_fp32", n_act * f_basis, "flop"),
         "ace.force": ("alu_fp32", n_act * f_force, "flop"),
+        "ace.backproject": ("alu_fp32", n_act * f_backproject, "flop"),
         "eam.density": ("hbm", n * (row + 24 + 8 + 32), "byte"),
         "eam.force": ("hbm", n * (row + 24 + 16 + 24), "byte"),
         "nbr.build": ("hbm", n * (24 + row), "byte"),

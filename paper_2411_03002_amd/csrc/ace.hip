@@ -604,6 +604,37 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
   }
 }
 
+// Back-projection of the adjoint of the float32 unit path, one tile of 64 atoms per block
+// (lane = atom): B[k][lm] = sum_n Wp[l][n][k] Abar[n][lm], read and written tile-major
+// [tile][a][64], so every load and store of a wave is one coalesced 256-byte segment; the
+// K loads of an output are issued together and the weights are wave-uniform scalar loads.
+// The sum runs over n in ascending order.
+template <class T, int LMAX>
+__global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ Abg, T* __restrict__ Bg,
+                                                         const T* __restrict__ Wp, int K, int na) {
+  constexpr int LM = (LMAX + 1) * (LMAX + 1);
+  constexpr int TILE = 64;
+  constexpr int kMaxK = 12;
+  const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const T* Ab = Abg + (size_t)blockIdx.x * na * TILE;
+  T* B = Bg + (size_t)blockIdx.x * na * TILE;
+  for (int o = wv; o < na; o += 4) {
+    const int kk = o / LM, lm = o - kk * LM;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    T a[kMaxK];
+#pragma unroll
+    for (int nn = 0; nn < kMaxK; ++nn) a[nn] = nn < K ? Ab[(size_t)(nn * LM + lm) * TILE + t] : T(0);
+    T v = T(0);
+#pragma unroll
+    for (int nn = 0; nn < kMaxK; ++nn) {
+      const T w = nn < K ? *(const __attribute__((address_space(4))) T*)(Wp + ((size_t)l * K + nn) * K + kk) : T(0);
+      v += w * a[nn];
+    }
+    B[(size_t)o * TILE + t] = v;
+  }
+}
+
 // ------------------------------------------------------------------ kernel 3
 template <class T, int LMAX>
 __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos, int n, BoxDev b,
@@ -624,8 +655,13 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   const int ts = sc.tile_size;
   const T* Abr = ts > 0 ? sc.Ab + (size_t)(q / ts) * na * ts + (q % ts) : sc.Ab + (size_t)q * na;
   const int as = ts > 0 ? ts : 1;
-  // back-projection: Ab2[k][lm] = sum_n Wp[l][n][k] Abar[n][lm]
-  for (int o = lane; o < K * LM; o += 64) {
+  // back-projection: Ab2[k][lm] = sum_n Wp[l][n][k] Abar[n][lm]; the float32 unit path
+  // has it precomputed tile-major in sc.A by k_ace_backproject
+  if (ts > 0) {
+    const T* B = sc.A + (size_t)(q / ts) * na * ts + (q % ts);
+    for (int o = lane; o < K * LM; o += 64) Ab2[o] = B[(size_t)o * ts];
+  }
+  for (int o = lane; o < K * LM && ts == 0; o += 64) {
     const int kk = o / LM, lm = o - kk * LM;
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
@@ -1297,6 +1333,11 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       return fail(ctx, APX_EINVAL, "ACE tile needs %zu bytes of LDS, the device allows %d (reduce n_max)",
                   lds_for(TILE / 2), lds_max);
     if (s != APX_OK) return s;
+  }
+  if (use_units) {
+    ProfScope ps(ctx, "ace.backproject");
+    k_ace_backproject<T, LMAX><<<(unsigned)(n_pad / TILE), 256, 0, ctx->stream>>>(sc.Ab, sc.A, tb.Wp, m->n_max, na);
+    APX_LAUNCH_CHECK(ctx);
   }
   const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
   ProfScope ps(ctx, "ace.force");
