@@ -43,6 +43,14 @@ struct AceScratch {
 };
 
 // ------------------------------------------------------------ shared helpers
+// Reads a read-only table entry (a scalar type) through the constant address space.  The
+// product kernels store to global memory, so the compiler cannot prove their table reads
+// unclobbered and would issue vector loads; constant-space reads let it use scalar loads.
+template <class X>
+__device__ __forceinline__ X cld(const X* p) {
+  return *(const __attribute__((address_space(4))) X*)p;
+}
+
 template <class T, int LMAX, bool GRAD>
 __device__ __forceinline__ void solid_harmonics(T x, T y, T z, T* S, T* Sx, T* Sy, T* Sz) {
   S[0] = T(1);
@@ -330,12 +338,12 @@ __device__ __forceinline__ void pair_fwd_deg(const T* __restrict__ As, const int
 #pragma unroll
       for (int n3 = 0; n3 < NMAX; ++n3) {
         if (n3 >= n30 && n3 < n3e) {
-          const Coef2<T> c = tb.tc[q0 + n3 - n30];
+          const Coef2<T>* c = tb.tc + (q0 + n3 - n30);
           T B = T(0);
 #pragma unroll
           for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
-          p1 = fma(c.c1, B, p1);
-          p2 = fma(c.c2, B, p2);
+          p1 = fma(cld(&c->c1), B, p1);
+          p2 = fma(cld(&c->c2), B, p2);
         }
       }
     }
@@ -796,13 +804,6 @@ __device__ __forceinline__ void gadd(T* __restrict__ Abt, int a, int t, T v) {
   unsafeAtomicAdd(&Abt[(size_t)a * TILE + t], v);
 }
 
-// Reads a read-only table entry (a scalar type) through the constant address space.  The adjoint kernels
-// store to global memory, so the compiler cannot prove their table reads unclobbered and
-// would issue vector loads; constant-space reads let it use scalar loads.
-template <class X>
-__device__ __forceinline__ X cld(const X* p) {
-  return *(const __attribute__((address_space(4))) X*)p;
-}
 
 // The third blocks of degree L in registers, and the flush of their adjoint.
 template <class T, int LMAX, int NMAX, int TILE, int L>
