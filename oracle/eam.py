@@ -9,6 +9,16 @@ the paper uses for its EAM2 pair and density functions, Appendix D):
     rho(r)   = exp(-beta (r - r0)) psi((r - r_c)/h)
     F(rho)   = -sqrt(rho)   (F = 0 at rho = 0)
 
+The paper's own EAM2 copper potential (Appendix D; parameter objects with the field
+``xi0``) is the second form:
+    Phi(r)  = (E1 M(r, r01, alpha1) + E2 M(r, r02, alpha2) + delta) psi((r - rc)/h)
+              - sum_n Theta(rs_n - r) S_n (rs_n - r)^4,
+    M(r, r0, alpha) = exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0)),
+    zeta(r) = (a exp(-beta1 (r - r03)^2) + exp(-beta2 (r - r04))) psi((r - rc)/h),
+    xi(x)   = xi0 + xi2 (x-1)^2 / 2 + sum_n q_n (x-1)^(n+2)                        for x <= 1,
+              (xi0 + xi2 (x-1)^2 / 2 + q1 (x-1)^3 + Q1 (x-1)^4) / (1 + Q2 (x-1)^3)   otherwise,
+    plus the energy offset f0 of the paper's refit (Sec. III B); Theta(0) = 1.
+
 Written with float64 torch tensors so that forces can be taken as the negative
 gradient of the weighted energy by autograd.
 """
@@ -24,15 +34,42 @@ def psi(x: torch.Tensor) -> torch.Tensor:
     return torch.where(x < 0.0, x4 / (1.0 + x4), torch.zeros_like(x))
 
 
+def _is_eam2(p) -> bool:
+    return hasattr(p, "xi0")
+
+
+def _morse(r, r0, alpha):
+    """M(r, r0, alpha) of Appendix D: exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))."""
+    return torch.exp(-2.0 * alpha * (r - r0)) - 2.0 * torch.exp(-alpha * (r - r0))
+
+
 def pair_phi(r: torch.Tensor, p) -> torch.Tensor:
+    if _is_eam2(p):
+        # Appendix D: (E1 M(r, r01, a1) + E2 M(r, r02, a2) + delta) psi((r - rc)/h)
+        #             - sum_n Theta(rs_n - r) S_n (rs_n - r)^4
+        v = (p.E1 * _morse(r, p.r01, p.alpha1) + p.E2 * _morse(r, p.r02, p.alpha2) + p.delta) * psi((r - p.rc) / p.h)
+        for S, rs in zip(p.S, p.rs):
+            v = v - torch.where(rs - r >= 0.0, S * (rs - r) ** 4, torch.zeros_like(r))
+        return v
     return p.A * torch.exp(-p.alpha * (r - p.r0)) * psi((r - p.rc) / p.h)
 
 
 def pair_rho(r: torch.Tensor, p) -> torch.Tensor:
+    if _is_eam2(p):
+        # Appendix D: (a exp(-beta1 (r - r03)^2) + exp(-beta2 (r - r04))) psi((r - rc)/h)
+        return (p.a * torch.exp(-p.beta1 * (r - p.r03) ** 2) + torch.exp(-p.beta2 * (r - p.r04))) * psi((r - p.rc) / p.h)
     return torch.exp(-p.beta * (r - p.r0)) * psi((r - p.rc) / p.h)
 
 
-def embed(rho: torch.Tensor) -> torch.Tensor:
+def embed(rho: torch.Tensor, p=None) -> torch.Tensor:
+    if p is not None and _is_eam2(p):
+        # Appendix D eq. mishin_embedding_function, plus the fit's offset (Sec. III B)
+        x = rho - 1.0
+        low = p.xi0 + 0.5 * p.xi2 * x ** 2
+        for k, qn in enumerate(p.q):
+            low = low + qn * x ** (k + 3)
+        high = (p.xi0 + 0.5 * p.xi2 * x ** 2 + p.q[0] * x ** 3 + p.Q1 * x ** 4) / (1.0 + p.Q2 * x ** 3)
+        return torch.where(rho <= 1.0, low, high) + p.f0
     safe = torch.where(rho > 0.0, rho, torch.ones_like(rho))
     return torch.where(rho > 0.0, -torch.sqrt(safe), torch.zeros_like(rho))
 
@@ -66,7 +103,7 @@ def site_energies(pos_t, box, periodic, i, j, p, n: int, sites=None) -> torch.Te
     it = torch.as_tensor(i)
     rho = torch.zeros(n, dtype=torch.float64).index_add(0, it, pair_rho(r, p))
     pair = torch.zeros(n, dtype=torch.float64).index_add(0, it, pair_phi(r, p))
-    e = embed(rho) + 0.5 * pair
+    e = embed(rho, p) + 0.5 * pair
     if sites is not None:
         m = torch.zeros(n, dtype=torch.bool)
         m[torch.as_tensor(sites)] = True

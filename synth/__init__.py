@@ -26,9 +26,12 @@ from .systems import (  # noqa: F401
 )
 from .params import (  # noqa: F401
     EamParams,
+    Eam2Params,
     AceParams,
     PrecisionParams,
     eam_cu_like,
+    eam2_original,
+    eam2_fit300k,
     eam_anchor,
     eam_label_anchor,
     ace_random,

@@ -29,6 +29,55 @@ class EamParams:
 
 
 @dataclasses.dataclass(frozen=True)
+class Eam2Params:
+    """The paper's EAM2 copper potential (Appendix D): pair potential Phi of two Morse-like
+    terms, a constant delta and three short-range repulsions S_n; density zeta of a
+    Gaussian and an exponential term; embedding xi piecewise around xi(1) = xi0, shifted
+    by f0 (the fit's energy offset, Sec. III B); taper psi((r - rc)/h)."""
+
+    E1: float
+    E2: float
+    delta: float
+    alpha1: float
+    alpha2: float
+    r01: float
+    r02: float
+    S: tuple
+    rs: tuple
+    a: float
+    beta1: float
+    beta2: float
+    r03: float
+    r04: float
+    xi0: float
+    xi2: float
+    q: tuple
+    Q1: float
+    Q2: float
+    f0: float
+    rc: float
+    h: float
+
+
+def eam2_original() -> Eam2Params:
+    """Appendix D, Table II, column 'Value original' (EAM2 of Mishin et al.)."""
+    return Eam2Params(E1=2.01458e+02, E2=6.59288e-03, delta=8.62250e-03, alpha1=2.97758e+00, alpha2=1.54927e+00,
+                      r01=8.35910e-01, r02=4.46867e+00, S=(4.0, 40.0, 1150.0), rs=(2.24, 1.80, 1.20),
+                      a=3.80362e+00, beta1=1.73940e-01, beta2=5.35661e+02, r03=-2.19885e+00, r04=-2.61984e+02,
+                      xi0=-2.30000e+00, xi2=1.40000e+00, q=(-1.30000e+00, -9.00000e-01, 1.80000e+00, 3.00000e+00),
+                      Q1=4.00000e-01, Q2=3.00000e-01, f0=0.0, rc=5.50679e+00, h=5.00370e-01)
+
+
+def eam2_fit300k() -> Eam2Params:
+    """Appendix D, Table II, column 'Value fit 300K' (the paper's refit, F_0^Fit included)."""
+    return Eam2Params(E1=2.01486e+02, E2=6.44057e-03, delta=2.18016e-02, alpha1=2.96972e+00, alpha2=1.55510e+00,
+                      r01=8.36347e-01, r02=4.46690e+00, S=(4.0, 40.0, 1150.0), rs=(2.24, 1.80, 1.20),
+                      a=3.80541e+00, beta1=1.66589e-01, beta2=5.35661e+02, r03=-2.19834e+00, r04=-2.61984e+02,
+                      xi0=-2.30089e+00, xi2=1.39912e+00, q=(-1.29894e+00, -8.99672e-01, 1.79940e+00, 2.99944e+00),
+                      Q1=3.99178e-01, Q2=3.00455e-01, f0=-1.50036e-01, rc=5.50679e+00, h=5.00370e-01)
+
+
+@dataclasses.dataclass(frozen=True)
 class AceParams:
     """Synthetic ACE: Chebyshev radial basis of ``n_max`` functions mixed by ``W``
     (shape ``[l_max+1, n_max, n_max]``), real spherical harmonics up to ``l_max``,
