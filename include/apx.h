@@ -165,11 +165,27 @@ apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* atoms, const
 
 /* ------------------------------------------------------------------- EAM */
 /* Sec. III B eq. energy_eam: E_i = F(rho_i) + 1/2 sum_j phi(r_ij), rho_i = sum_j rho(r_ij)
- * over r_ij < r_cut, with phi(r) = A exp(-alpha(r - r0)) psi((r - r_cut)/h),
- * rho(r) = exp(-beta(r - r0)) psi((r - r_cut)/h), psi(x) = x^4/(1 + x^4) for x < 0
- * else 0 (the taper of Appendix D), F(rho) = -sqrt(rho). */
+ * over r_ij < r_cut, psi(x) = x^4/(1 + x^4) for x < 0 else 0 (the taper of Appendix D).
+ * kind APX_EAM_CLOSED: phi(r) = A exp(-alpha(r - r0)) psi((r - r_cut)/h),
+ *     rho(r) = exp(-beta(r - r0)) psi((r - r_cut)/h), F(rho) = -sqrt(rho).
+ * kind APX_EAM2: the paper's EAM2 copper potential (Appendix D, parameters of Table II;
+ *     the refit's offset of Sec. III B added to the embedding), eam2[] holding in order
+ *     E1, E2, delta, alpha1, alpha2, r01, r02, S1, S2, S3, rs1, rs2, rs3, a, beta1, beta2,
+ *     r03, r04, xi0, xi2, q1, q2, q3, q4, Q1, Q2, f0:
+ *     phi(r)  = (E1 M(r, r01, alpha1) + E2 M(r, r02, alpha2) + delta) psi((r - r_cut)/h)
+ *               - sum_n [r <= rs_n] S_n (rs_n - r)^4,
+ *     M(r, r0, alpha) = exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0)),
+ *     rho(r)  = (a exp(-beta1 (r - r03)^2) + exp(-beta2 (r - r04))) psi((r - r_cut)/h),
+ *     F(x)    = xi0 + xi2 d^2/2 + sum_n q_n d^(n+2) for x <= 1, else
+ *               (xi0 + xi2 d^2/2 + q1 d^3 + Q1 d^4)/(1 + Q2 d^3), d = x - 1; plus f0.
+ * A, alpha, beta, r0 are unused for APX_EAM2. */
+#define APX_EAM_CLOSED 0
+#define APX_EAM2 1
 typedef struct {
   double A, alpha, beta, r0, r_cut, h;
+  int32_t kind;
+  int32_t reserved;
+  double eam2[27];
 } apx_eam_params;
 
 /* Outputs: e_site[n] = E_i^EAM (unweighted), rho[n], f[3][n] (overwritten) =
@@ -187,7 +203,8 @@ apx_status apx_eam_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist*
  * p = n(l_max+1) + l, p1 <= p2 <= p3, l1+l2+l3 even, triangle: sum G A A A with the
  * real Gaunt coefficients.  Basis order: B1 (n), B2 (n1, n2, l), B3 (p1, p2, p3).
  * sqrt is replaced by F_eps(x) = sign(x)(sqrt(|x| + eps^2) - eps).  If `anchored`, an
- * EAM site energy with parameters `anchor` is added to E_i. */
+ * EAM site energy with parameters `anchor` (kind APX_EAM_CLOSED; EINVAL otherwise) is added
+ * to E_i. */
 typedef struct {
   int32_t n_max;    /* 1..12 */
   int32_t l_max;    /* 3 or 4 */

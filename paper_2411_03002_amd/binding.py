@@ -42,9 +42,13 @@ class PrecParams(C.Structure):
                 ("r_cut", C.c_double), ("r_lo", C.c_double), ("r_hi", C.c_double)]
 
 
+EAM_CLOSED, EAM2 = 0, 1
+
+
 class EamParams(C.Structure):
     _fields_ = [("A", C.c_double), ("alpha", C.c_double), ("beta", C.c_double), ("r0", C.c_double),
-                ("r_cut", C.c_double), ("h", C.c_double)]
+                ("r_cut", C.c_double), ("h", C.c_double), ("kind", C.c_int32), ("reserved", C.c_int32),
+                ("eam2", C.c_double * 27)]
 
 
 class AceDesc(C.Structure):

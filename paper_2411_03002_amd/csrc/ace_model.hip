@@ -380,6 +380,8 @@ extern "C" apx_status apx_ace_model_create(apx_ctx* ctx, const apx_ace_desc* d, 
   if (d->n_max < 1 || d->n_max > 12) return fail(ctx, APX_EINVAL, "n_max must be in 1..12");
   if (d->l_max != 3 && d->l_max != 4) return fail(ctx, APX_EINVAL, "l_max must be 3 or 4");
   if (!d->W || !d->c1 || !d->c2) return fail(ctx, APX_EINVAL, "W, c1 and c2 are required");
+  if (d->anchored && d->anchor.kind != APX_EAM_CLOSED)
+    return fail(ctx, APX_EINVAL, "the EAM anchor of an ACE model must use the closed form");
   if (!(d->r_cut > 0.0) || !(d->h > 0.0) || !(d->s_a > 0.0) || !(d->eps > 0.0))
     return fail(ctx, APX_EINVAL, "r_cut, h, s_a and eps must be positive");
   Catalogue c;

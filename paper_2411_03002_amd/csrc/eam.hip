@@ -1,6 +1,7 @@
 // Embedded-atom model: density/embedding pass and site-weighted force pass.
 //
-// Sec. III B eq. energy_eam with the closed-form synthetic functions; forces are the
+// Sec. III B eq. energy_eam with the closed-form synthetic functions or the paper's EAM2
+// copper potential (Appendix D), chosen at compile time per launch; forces are the
 // fast-potential part of Appendix C eq. F_i_d:
 //   F_i = -d/dx_i sum_k u_k E_k,  u = 1 - w
 //       = sum_j [ 1/2 (u_i + u_j) phi'(r_ij) + (u_i F'_i + u_j F'_j) rho'(r_ij) ] r_ij / r_ij
@@ -15,6 +16,9 @@ namespace apx {
 
 struct EamDev {
   double A, alpha, beta, r0, rc, inv_h, rc2;
+  // EAM2 (Appendix D), in the order of apx_eam_params.eam2
+  double E1, E2, delta, alpha1, alpha2, r01, r02, S[3], rs[3], a, beta1, beta2, r03, r04, xi0, xi2, q[4], Q1, Q2,
+      f0;
 };
 
 // psi(x) = x^4/(1+x^4) for x < 0 and its derivative d psi/dx.
@@ -26,11 +30,57 @@ __device__ __forceinline__ void taper(double x, double& p, double& dp) {
   dp = 4.0 * x2 * x * den * den;
 }
 
+// EAM2 pair functions at r (tapered parts with the taper value ps and slope dps, dps
+// already divided by h): pair potential Phi, density zeta and their derivatives.
+__device__ __forceinline__ void eam2_pair(const EamDev& p, double r, double ps, double dps, double& phi,
+                                          double& dphi, double& rho, double& drho) {
+  const double t1 = exp(-p.alpha1 * (r - p.r01)), t2 = exp(-p.alpha2 * (r - p.r02));
+  const double m1 = t1 * t1 - 2.0 * t1, m2 = t2 * t2 - 2.0 * t2;
+  const double dm1 = 2.0 * p.alpha1 * (t1 - t1 * t1), dm2 = 2.0 * p.alpha2 * (t2 - t2 * t2);
+  const double core = p.E1 * m1 + p.E2 * m2 + p.delta;
+  phi = core * ps;
+  dphi = (p.E1 * dm1 + p.E2 * dm2) * ps + core * dps;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = p.rs[k] - r;
+    if (d >= 0.0) {
+      const double d2 = d * d;
+      phi -= p.S[k] * d2 * d2;
+      dphi += 4.0 * p.S[k] * d2 * d;
+    }
+  }
+  const double x3 = r - p.r03;
+  const double g = p.a * exp(-p.beta1 * x3 * x3);
+  const double e = exp(-p.beta2 * (r - p.r04));
+  rho = (g + e) * ps;
+  drho = (-2.0 * p.beta1 * x3 * g - p.beta2 * e) * ps + (g + e) * dps;
+}
+
+// EAM2 embedding xi(x) + f0 and its slope.
+__device__ __forceinline__ void eam2_embed(const EamDev& p, double x, double& F, double& Fp) {
+  const double d = x - 1.0;
+  const double d2 = d * d, d3 = d2 * d;
+  if (x <= 1.0) {
+    const double d4 = d2 * d2, d5 = d4 * d, d6 = d3 * d3;
+    F = p.xi0 + 0.5 * p.xi2 * d2 + p.q[0] * d3 + p.q[1] * d4 + p.q[2] * d5 + p.q[3] * d6;
+    Fp = p.xi2 * d + 3.0 * p.q[0] * d2 + 4.0 * p.q[1] * d3 + 5.0 * p.q[2] * d4 + 6.0 * p.q[3] * d5;
+  } else {
+    const double N = p.xi0 + 0.5 * p.xi2 * d2 + p.q[0] * d3 + p.Q1 * d2 * d2;
+    const double Np = p.xi2 * d + 3.0 * p.q[0] * d2 + 4.0 * p.Q1 * d3;
+    const double D = 1.0 + p.Q2 * d3;
+    const double Dp = 3.0 * p.Q2 * d2;
+    F = N / D;
+    Fp = (Np * D - N * Dp) / (D * D);
+  }
+  F += p.f0;
+}
+
 // Neighbours are processed in batches of kBatch: the batch's indices and positions are
 // loaded first so that their memory accesses are in flight together, then the pairs are
 // summed in list order (the same order as one at a time).
 constexpr int kBatch = 8;
 
+template <int KIND>
 __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ pos, int n, BoxDev b, EamDev p,
                                                      const int* __restrict__ count, const int* __restrict__ idx,
                                                      int max_nb, const double* __restrict__ w,
@@ -63,21 +113,35 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
         const double r = sqrt(r2);
         double ps, dps;
         taper((r - p.rc) * p.inv_h, ps, dps);
-        rho += exp(-p.beta * (r - p.r0)) * ps;
-        pair += exp(-p.alpha * (r - p.r0)) * ps;
+        if constexpr (KIND == APX_EAM_CLOSED) {
+          rho += exp(-p.beta * (r - p.r0)) * ps;
+          pair += exp(-p.alpha * (r - p.r0)) * ps;
+        } else {
+          double phi, dphi, rr, drr;
+          eam2_pair(p, r, ps, dps * p.inv_h, phi, dphi, rr, drr);
+          rho += rr;
+          pair += phi;
+        }
       }
     }
   }
-  const double sq = sqrt(rho);
-  const double F = rho > 0.0 ? -sq : 0.0;
-  const double Fp = rho > 0.0 ? -0.5 / sq : 0.0;
-  e_site[i] = F + 0.5 * p.A * pair;
+  double F, Fp;
+  if constexpr (KIND == APX_EAM_CLOSED) {
+    const double sq = sqrt(rho);
+    F = rho > 0.0 ? -sq : 0.0;
+    Fp = rho > 0.0 ? -0.5 / sq : 0.0;
+    e_site[i] = F + 0.5 * p.A * pair;
+  } else {
+    eam2_embed(p, rho, F, Fp);
+    e_site[i] = F + 0.5 * pair;
+  }
   if (rho_out) rho_out[i] = rho;
   const double u = w ? 1.0 - w[i] : 1.0;
   ufp[i] = u * Fp;
   u_out[i] = u;
 }
 
+template <int KIND>
 __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ pos, int n, BoxDev b, EamDev p,
                                                    const int* __restrict__ count, const int* __restrict__ idx,
                                                    int max_nb, const double* __restrict__ ufp,
@@ -113,10 +177,16 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
         double ps, dps;
         taper((r - p.rc) * p.inv_h, ps, dps);
         dps *= p.inv_h;
-        const double eb = exp(-p.beta * (r - p.r0));
-        const double ea = exp(-p.alpha * (r - p.r0));
-        const double drho = eb * (dps - p.beta * ps);
-        const double dphi = p.A * ea * (dps - p.alpha * ps);
+        double drho, dphi;
+        if constexpr (KIND == APX_EAM_CLOSED) {
+          const double eb = exp(-p.beta * (r - p.r0));
+          const double ea = exp(-p.alpha * (r - p.r0));
+          drho = eb * (dps - p.beta * ps);
+          dphi = p.A * ea * (dps - p.alpha * ps);
+        } else {
+          double phi, rr;
+          eam2_pair(p, r, ps, dps, phi, dphi, rr, drho);
+        }
         const double s = 0.5 * (ui + uj[q]) * dphi + (ufi + fj[q]) * drho;
         const double sr = s / r;
         fx += sr * dx;
@@ -137,6 +207,7 @@ apx_status eam_check(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, 
   if (nl->n != atoms->n) return fail(ctx, APX_EINVAL, "nlist size mismatch");
   if (!(p->r_cut > 0.0) || p->r_cut > nl->r_list) return fail(ctx, APX_EINVAL, "EAM cutoff must be in (0, r_list]");
   if (!(p->h > 0.0)) return fail(ctx, APX_EINVAL, "EAM taper width must be positive");
+  if (p->kind != APX_EAM_CLOSED && p->kind != APX_EAM2) return fail(ctx, APX_EINVAL, "unknown EAM kind %d", p->kind);
   return APX_OK;
 }
 
@@ -149,6 +220,15 @@ EamDev eam_dev(const apx_eam_params* p) {
   d.rc = p->r_cut;
   d.inv_h = 1.0 / p->h;
   d.rc2 = p->r_cut * p->r_cut;
+  const double* e = p->eam2;
+  d.E1 = e[0]; d.E2 = e[1]; d.delta = e[2]; d.alpha1 = e[3]; d.alpha2 = e[4]; d.r01 = e[5]; d.r02 = e[6];
+  for (int k = 0; k < 3; ++k) {
+    d.S[k] = e[7 + k];
+    d.rs[k] = e[10 + k];
+  }
+  d.a = e[13]; d.beta1 = e[14]; d.beta2 = e[15]; d.r03 = e[16]; d.r04 = e[17]; d.xi0 = e[18]; d.xi2 = e[19];
+  for (int k = 0; k < 4; ++k) d.q[k] = e[20 + k];
+  d.Q1 = e[24]; d.Q2 = e[25]; d.f0 = e[26];
   return d;
 }
 
@@ -161,13 +241,22 @@ apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
   EamDev d = eam_dev(p);
   {
   ProfScope ps(ctx, "eam.density");
-  k_eam_density<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb,
-                                                             w, e_site, rho, ufp, u);
+  if (p->kind == APX_EAM2)
+    k_eam_density<APX_EAM2><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx,
+                                                                         nl->max_nb, w, e_site, rho, ufp, u);
+  else
+    k_eam_density<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
+                                                                               nl->idx, nl->max_nb, w, e_site, rho,
+                                                                               ufp, u);
   APX_LAUNCH_CHECK(ctx);
   }
   ProfScope ps(ctx, "eam.force");
-  k_eam_force<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb,
-                                                           ufp, u, f);
+  if (p->kind == APX_EAM2)
+    k_eam_force<APX_EAM2><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx,
+                                                                       nl->max_nb, ufp, u, f);
+  else
+    k_eam_force<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
+                                                                             nl->idx, nl->max_nb, ufp, u, f);
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
 }

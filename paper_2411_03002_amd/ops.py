@@ -162,10 +162,20 @@ def prec_struct(p, csp_given: bool = False) -> B.PrecParams:
 
 
 def eam_struct(p) -> B.EamParams:
+    """apx_eam_params of a closed-form parameter object, or of an EAM2 one (field ``xi0``)."""
     s = B.EamParams()
-    s.A, s.alpha, s.beta, s.r0 = float(p.A), float(p.alpha), float(p.beta), float(p.r0)
     s.r_cut = float(getattr(p, "rc", getattr(p, "r_cut", 5.0)))
     s.h = float(p.h)
+    if hasattr(p, "xi0"):
+        s.kind = B.EAM2
+        vals = [p.E1, p.E2, p.delta, p.alpha1, p.alpha2, p.r01, p.r02, *p.S, *p.rs, p.a, p.beta1, p.beta2, p.r03,
+                p.r04, p.xi0, p.xi2, *p.q, p.Q1, p.Q2, p.f0]
+        assert len(vals) == 27
+        for k, v in enumerate(vals):
+            s.eam2[k] = float(v)
+        return s
+    s.kind = B.EAM_CLOSED
+    s.A, s.alpha, s.beta, s.r0 = float(p.A), float(p.alpha), float(p.beta), float(p.r0)
     return s
 
 

@@ -134,18 +134,43 @@ def test_precision_bit_exact(ops_ctx, case):
     assert 0 < pr["n_active"] <= s.n
 
 
-@pytest.mark.parametrize("name", ["cfg0", "slab100_4x4x6"])
-def test_eam_parity(ops_ctx, name):
+def _compressed(s, f):
+    """The system with every length scaled by f (positions relative to lo)."""
+    lo = np.asarray(s.lo, dtype=np.float64)
+    pos = lo[:, None] + f * (s.pos - lo[:, None])
+    return synth.System(pos, lo, lo + f * (np.asarray(s.hi) - lo), s.periodic, frozen=s.frozen)
+
+
+# (system, potential, neighbour-list cutoff): the closed form and the paper's EAM2 copper
+# potential (cutoff 5.507 A); the compressed crystal reaches the EAM2 short-range terms
+# (nearest neighbours at 2.2 A < rs_1 = 2.24 A) and density above one
+EAM_CASES = {
+    "cfg0_closed": ("cfg0", synth.eam_cu_like, 5.5),
+    "slab_closed": ("slab100_4x4x6", synth.eam_cu_like, 5.5),
+    "cfg0_eam2_fit": ("cfg0", synth.eam2_fit300k, 6.0),
+    "slab_eam2_original": ("slab100_4x4x6", synth.eam2_original, 6.0),
+    "void_eam2_fit": ("void_bulk8", synth.eam2_fit300k, 6.0),
+    "cfg0_compressed_eam2_original": ("cfg0_compressed", synth.eam2_original, 5.6),
+}
+
+
+@pytest.mark.parametrize("case", list(EAM_CASES))
+def test_eam_parity(ops_ctx, case):
     ops, ctx = ops_ctx
-    _case(f"eam {name}")
-    s = SYSTEMS[name]
+    _case(f"eam {case}")
+    name, make, rl = EAM_CASES[case]
+    s = _compressed(SYSTEMS["cfg0"], 0.86) if name == "cfg0_compressed" else SYSTEMS[name]
+    prm = make()
     w = np.random.default_rng(3).uniform(size=s.n)
     w[::3] = 0.0
     atoms = ops.device_atoms(s)
-    nl = ops.build_neighbors(ctx, atoms, 5.5)
-    e = ops.eam_forces(ctx, atoms, nl, synth.eam_cu_like(), torch.as_tensor(w, device="cuda"))
-    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
-    ref = hybrid.evaluate(s, synth.eam_cu_like(), None, w, csr)
+    nl = ops.build_neighbors(ctx, atoms, rl, max_nb=128)
+    e = ops.eam_forces(ctx, atoms, nl, prm, torch.as_tensor(w, device="cuda"))
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, rl)
+    ref = hybrid.evaluate(s, prm, None, w, csr)
+    if name == "cfg0_compressed":
+        i, j = geometry.pairs_within(s.pos, s.lo, s.hi, s.periodic, prm.rs[0], csr)
+        assert i.size > 0
     assert np.allclose(e["e_site"].cpu().numpy(), ref["e_eam"], atol=FTOL, rtol=0)
     assert np.allclose(e["rho"].cpu().numpy(), ref["rho"], atol=FTOL, rtol=0)
     assert np.allclose(e["f"].cpu().numpy(), ref["f_eam"], atol=FTOL, rtol=0)
