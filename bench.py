@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-full", action="store_true", help="skip the full-ACE comparison")
     ap.add_argument("--no-avg", action="store_true", help="skip the time-averaged-weights run")
+    ap.add_argument("--no-eam2", action="store_true", help="skip the EAM2 timing")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the adaptive timed region (for external profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -359,6 +360,31 @@ def main():
                          if k in prof_t},
         }
         log(f"time-averaged {dt_t / K * 1e3:.3f} ms/step, active mean {st_t['ace_atoms'] / K:.0f}")
+
+    if not args.no_eam2:
+        # the paper's EAM2 copper potential (refit) on the same block: its cutoff of
+        # 5.507 A needs a 6-A list (about 78 neighbours in the bulk)
+        log("EAM2 (paper's refit) density and force passes")
+        nl6 = ops.build_neighbors(ctx, atoms, 6.0, max_nb=96)
+        eam2 = synth.eam2_fit300k()
+        ops.eam_forces(ctx, atoms, nl6, eam2)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(5):
+            ops.eam_forces(ctx, atoms, nl6, eam2)
+        torch.cuda.synchronize()
+        prof_e = ctx.profile_read()
+        ctx.profile(False)
+        m6 = kernel_models(stats, n, 0, 78.0, 0.0)
+        result["eam2"] = {
+            "potential": "EAM2 copper, refit parameters (Appendix D, Table II)", "r_list": 6.0,
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_e.items()
+                        if k.startswith("eam.")},
+            "roofline": {k: roofline_for(k, m6[k], *prof_e[k]) for k in ("eam.density", "eam.force") if k in prof_e},
+        }
+        del nl6
+        torch.cuda.empty_cache()
+        log("EAM2 " + ", ".join(f"{k} {v['avg_ms']:.3f} ms" for k, v in result["eam2"]["kernels"].items()))
 
     if not args.no_full:
         log(f"full ACE: 1 warm-up + {KF} timed steps")

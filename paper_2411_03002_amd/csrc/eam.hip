@@ -51,7 +51,10 @@ __device__ __forceinline__ void eam2_pair(const EamDev& p, double r, double ps, 
   }
   const double x3 = r - p.r03;
   const double g = p.a * exp(-p.beta1 * x3 * x3);
-  const double e = exp(-p.beta2 * (r - p.r04));
+  // exp(-x) is +0 in double precision for x above 745.2; the refit's second density
+  // term (beta2 = 535.661 /A, r04 = -261.984 A) is always there, so it is skipped
+  const double xe = p.beta2 * (r - p.r04);
+  const double e = xe > 746.0 ? 0.0 : exp(-xe);
   rho = (g + e) * ps;
   drho = (-2.0 * p.beta1 * x3 * g - p.beta2 * e) * ps + (g + e) * dps;
 }

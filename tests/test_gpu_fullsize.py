@@ -246,3 +246,32 @@ def test_indentation_block_time_averaged_weights(ops_ctx):
         print(f"sample {k}: detected {int(o['mask'].sum())}, held by the minimum step "
               f"{int(np.sum(o['w'] != o['w_avg']))}", flush=True)
     torch.cuda.empty_cache()
+
+
+def test_indentation_block_eam2_sampled(ops_ctx):
+    """The paper's EAM2 copper potential (refit) on the 4,000,000-atom block, as the
+    benchmark times it (6-A list): site energies and forces of sampled atoms against the
+    oracle on clusters cut at 2 r_c + 0.6 A, with random weights."""
+    ops, ctx = ops_ctx
+    print("\n[case] full size: 100^3-cell indentation block, EAM2 sampled parity", flush=True)
+    s = configs.cfg2()
+    prm = synth.eam2_fit300k()
+    rng = np.random.default_rng(23)
+    w = rng.uniform(size=s.n)
+    w[rng.uniform(size=s.n) < 0.5] = 0.0
+    atoms = ops.device_atoms(s)
+    nl = ops.build_neighbors(ctx, atoms, 6.0, max_nb=96)
+    e = ops.eam_forces(ctx, atoms, nl, prm, torch.as_tensor(w, device="cuda"))
+    e_site = e["e_site"].cpu().numpy()
+    f = e["f"].cpu().numpy()
+    cut = Cutter(s)
+    smp = np.concatenate([rng.choice(s.n, 8, replace=False), np.nonzero(s.frozen)[0][:2],
+                          np.argsort(s.pos[2])[-2:]])
+    for i in smp:
+        cl, idx, c = cut.cluster(i, 2 * prm.rc + 0.6)
+        ev = hybrid.evaluate(cl, prm, None, w[idx])
+        assert abs(e_site[i] - ev["e_eam"][c]) < FTOL, i
+        assert np.max(np.abs(f[:, i] - ev["f_eam"][:, c])) < FTOL, (i, f[:, i], ev["f_eam"][:, c])
+    print(f"{smp.size} sampled atoms", flush=True)
+    del nl
+    torch.cuda.empty_cache()
