@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-full", action="store_true", help="skip the full-ACE comparison")
     ap.add_argument("--no-avg", action="store_true", help="skip the time-averaged-weights run")
     ap.add_argument("--no-eam2", action="store_true", help="skip the EAM2 timing")
+    ap.add_argument("--no-hyb2", action="store_true", help="skip the Hyb2 run")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the adaptive timed region (for external profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,8 +271,8 @@ def main():
     stats = model.stats()
     vel0 = torch.as_tensor(s.vel, dtype=torch.float64, device="cuda").contiguous()
 
-    def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0):
-        md = ops.MD(ctx, atoms, eam_p, model, prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
+    def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0, prec_set=None):
+        md = ops.MD(ctx, atoms, eam_p, model, prec_set or prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
                     ace_precision="fp32", mode=mode, indenter=ind, avg_samples=avg_samples, avg_dw_min=avg_dw_min)
         pos = atoms.pos.clone()
         vel = vel0.clone()
@@ -360,6 +361,16 @@ def main():
                          if k in prof_t},
         }
         log(f"time-averaged {dt_t / K * 1e3:.3f} ms/step, active mean {st_t['ace_atoms'] / K:.0f}")
+
+    if not args.no_hyb2:
+        # the paper's Hyb2 set: spreading radii 8/20 A instead of 4/12 A
+        log(f"Hyb2 weights: {W} warm-up + {K} timed steps")
+        dt_h, st_h, prof_h, tim_h = run("adaptive", K, W, False, prec_set=synth.precision_hyb2())
+        result["hyb2"] = {"r_lo": 8.0, "r_hi": 20.0, "atom_steps_per_s": n * K / dt_h, "ms_per_step": dt_h / K * 1e3,
+                          "active_atoms_mean": st_h["ace_atoms"] / K,
+                          "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
+                                                        [t / K for t in tim_h]))}
+        log(f"Hyb2 {dt_h / K * 1e3:.3f} ms/step, active mean {st_h['ace_atoms'] / K:.0f}")
 
     if not args.no_eam2:
         # the paper's EAM2 copper potential (refit) on the same block: its cutoff of

@@ -38,6 +38,7 @@ from .params import (  # noqa: F401
     ace_label_model,
     precision_cfg0,
     precision_hyb1,
+    precision_hyb2,
     precision_static,
 )
 from . import configs  # noqa: F401

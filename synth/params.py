@@ -162,8 +162,14 @@ def precision_cfg0() -> PrecisionParams:
 
 
 def precision_hyb1() -> PrecisionParams:
-    """The paper's Hyb1 set: CSP 2.5/3.0 A^2, f_cut switch, spreading radii 4/12 A."""
+    """The paper's Hyb1 set (Table IV): CSP 2.5/3.0 A^2, f_cut switch, spreading radii 4/12 A.
+    Its time averages (N = 110 samples, minimum step 1/N) are integrator settings."""
     return PrecisionParams(csp_lo=2.5, csp_hi=3.0, switch_kind=1, r_lo=4.0, r_hi=12.0)
+
+
+def precision_hyb2() -> PrecisionParams:
+    """The paper's Hyb2 set (Appendix H): Hyb1 with spreading radii 8/20 A."""
+    return PrecisionParams(csp_lo=2.5, csp_hi=3.0, switch_kind=1, r_lo=8.0, r_hi=20.0)
 
 
 def precision_static() -> PrecisionParams:

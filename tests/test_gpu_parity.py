@@ -39,6 +39,8 @@ def _systems():
         "cfg0_static": configs.cfg0_static(),
         "slab100_4x4x6": configs.slab100(4, 4, 6, seed=5, temperature=300.0, sigma=0.05),
         "void_bulk8": configs.bulk(8, seed=6, temperature=300.0, void_radius=6.0),
+        # 43.4-A periodic box: room for the Hyb2 spreading radius of 20 A
+        "bulk12_vac": configs.bulk(12, seed=9, temperature=100.0, vacancies=1),
     }
     return out
 
@@ -112,6 +114,7 @@ PREC_CASES = {
     "cfg0_static_spread": ("cfg0_static", synth.precision_static()),
     "slab_hyb1_spread": ("slab100_4x4x6", synth.PrecisionParams(2.5, 3.0, 1, 4.0, 8.0)),
     "void_hyb1_spread": ("void_bulk8", synth.PrecisionParams(2.5, 3.0, 1, 4.0, 8.0)),
+    "bulk12_vac_hyb2": ("bulk12_vac", synth.precision_hyb2()),
 }
 
 
