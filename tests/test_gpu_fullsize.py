@@ -275,3 +275,29 @@ def test_indentation_block_eam2_sampled(ops_ctx):
     print(f"{smp.size} sampled atoms", flush=True)
     del nl
     torch.cuda.empty_cache()
+
+
+def test_integrator_with_eam2_conserves_energy():
+    """The integrator with the paper's EAM2 (refit) as its potential, EAM-only mode, on a
+    thermal 12^3-cell crystal: 200 steps of 1 fs conserve the total energy to the Verlet
+    fluctuation (the list cutoff follows the 5.507-A EAM2 cutoff plus the skin)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_03002_amd import ops
+    print("\n[case] integrator, EAM2, 12^3 cells, 200 steps", flush=True)
+    ctx = ops.Context(0)
+    s = configs.bulk(12, seed=41, temperature=300.0, velocities=True)
+    atoms = ops.device_atoms(s)
+    md = ops.MD(ctx, atoms, synth.eam2_fit300k(), None, None, dt=1e-3, skin=0.5, max_nb=96, precision_every=0,
+                mode="eam")
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(s.vel, device="cuda").contiguous()
+    f, w = md.init(pos)
+    energies = []
+    for _ in range(20):
+        st = md.step(pos, vel, f, w, 10)
+        energies.append(st["e_pot"] + st["e_kin"])
+    md.close()
+    spread = (max(energies) - min(energies)) / s.n
+    print(f"energy spread {spread:.3e} eV/atom, rebuilds {st['rebuilds']}", flush=True)
+    assert spread < 3e-5
