@@ -23,7 +23,7 @@ __host__ __device__ constexpr int unit_group(int L) { return L < 0 ? 0 : L; }
 // ints per adjoint unit record: type, L (-1: a B1/B2 unit), first pair (B1/B2: the label
 // n1), end pair, first other label, first and end entry of the unit's pair stream, end
 // other label (the unit holds the pairs whose other label lies in [first, end), a range
-// of at most (n_max + 1)/2 labels).
+// of at most unit_width(L, n_max) labels).
 constexpr int kUnitRec = 8;
 // Widest range of other labels an adjoint unit of launch group g may hold (the unit
 // accumulates their adjoints in registers; narrower ranges leave registers to the larger
