@@ -614,9 +614,10 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
 
 // Back-projection of the adjoint of the float32 unit path, one tile of 64 atoms per block
 // (lane = atom): B[k][lm] = sum_n Wp[l][n][k] Abar[n][lm], read and written tile-major
-// [tile][a][64], so every load and store of a wave is one coalesced 256-byte segment; the
-// K loads of an output are issued together and the weights are wave-uniform scalar loads.
-// The sum runs over n in ascending order.
+// [tile][a][64], so every load and store of a wave is one coalesced 256-byte segment.  A
+// wave takes columns lm = wave, wave + 4, ...; a column's K adjoint values are loaded once
+// and serve its K outputs, and the weights are wave-uniform scalar loads.  The sum runs
+// over n in ascending order.
 template <class T, int LMAX>
 __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ Abg, T* __restrict__ Bg,
                                                          const T* __restrict__ Wp, int K, int na) {
@@ -626,20 +627,20 @@ __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ A
   const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const T* Ab = Abg + (size_t)blockIdx.x * na * TILE;
   T* B = Bg + (size_t)blockIdx.x * na * TILE;
-  for (int o = wv; o < na; o += 4) {
-    const int kk = o / LM, lm = o - kk * LM;
+  for (int lm = wv; lm < LM; lm += 4) {
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
     T a[kMaxK];
 #pragma unroll
     for (int nn = 0; nn < kMaxK; ++nn) a[nn] = nn < K ? Ab[(size_t)(nn * LM + lm) * TILE + t] : T(0);
-    T v = T(0);
+    for (int kk = 0; kk < K; ++kk) {
+      T v = T(0);
 #pragma unroll
-    for (int nn = 0; nn < kMaxK; ++nn) {
-      const T w = nn < K ? *(const __attribute__((address_space(4))) T*)(Wp + ((size_t)l * K + nn) * K + kk) : T(0);
-      v += w * a[nn];
+      for (int nn = 0; nn < kMaxK; ++nn) {
+        if (nn < K) v += *(const __attribute__((address_space(4))) T*)(Wp + ((size_t)l * K + nn) * K + kk) * a[nn];
+      }
+      B[(size_t)(kk * LM + lm) * TILE + t] = v;
     }
-    B[(size_t)o * TILE + t] = v;
   }
 }
 
