@@ -159,22 +159,24 @@ def _single_env(nbrs):
     return synth.System(pos, np.full(3, -50.0), np.full(3, 50.0), (0, 0, 0))
 
 
-def test_b2_addition_theorem():
+@pytest.mark.parametrize("nl", [(8, 3), (10, 4)])
+def test_b2_addition_theorem(nl):
+    n_max, l_max = nl
     rng = np.random.default_rng(3)
     nb = rng.normal(size=(7, 3))
     nb *= (rng.uniform(2.2, 4.8, 7) / np.linalg.norm(nb, axis=1))[:, None]
     s = _single_env(nb)
-    prm = _ace(8, 3)
+    prm = _ace(n_max, l_max)
     i, j = geometry.pairs_within(s.pos, s.lo, s.hi, s.periodic, prm.rc)
     A_ = ace.atomic_base(torch.as_tensor(s.pos), s.box, s.periodic, i, j, prm, [0])
-    B = ace.product_basis(A_, 8, 3)[0].numpy()
+    B = ace.product_basis(A_, n_max, l_max)[0].numpy()
     r = np.linalg.norm(nb, axis=1)
     u = nb / r[:, None]
-    g = ace.chebyshev_radial(torch.as_tensor(r), 8, 5.0, 0.5).numpy()
-    col = 8
-    for n1 in range(8):
-        for n2 in range(n1, 8):
-            for l in range(4):
+    g = ace.chebyshev_radial(torch.as_tensor(r), n_max, 5.0, 0.5).numpy()
+    col = n_max
+    for n1 in range(n_max):
+        for n2 in range(n1, n_max):
+            for l in range(l_max + 1):
                 R1 = g @ prm.W[l, n1]
                 R2 = g @ prm.W[l, n2]
                 Pl = np.polynomial.legendre.legval(u @ u.T, [0] * l + [1])
@@ -183,24 +185,50 @@ def test_b2_addition_theorem():
                 col += 1
 
 
-def test_b3_single_neighbour_closed_form():
+@pytest.mark.parametrize("nl", [(8, 3), (10, 4)])
+def test_b3_single_neighbour_closed_form(nl):
+    """One neighbour in a generic direction: every real Gaunt entry, m != 0 included,
+    enters sum_m G Y Y Y, which the closed form fixes through (l1 l2 l3; 0 0 0)^2."""
+    n_max, l_max = nl
     v = np.array([[1.3, -2.0, 1.7]])
     s = _single_env(v)
-    prm = _ace(8, 3)
+    prm = _ace(n_max, l_max)
     i, j = geometry.pairs_within(s.pos, s.lo, s.hi, s.periodic, prm.rc)
     A_ = ace.atomic_base(torch.as_tensor(s.pos), s.box, s.periodic, i, j, prm, [0])
-    B = ace.product_basis(A_, 8, 3)[0].numpy()
+    B = ace.product_basis(A_, n_max, l_max)[0].numpy()
     r = np.linalg.norm(v)
-    g = ace.chebyshev_radial(torch.tensor([r]), 8, 5.0, 0.5).numpy()[0]
-    spec = ace.basis_spec(8, 3)
+    g = ace.chebyshev_radial(torch.tensor([r]), n_max, 5.0, 0.5).numpy()[0]
+    spec = ace.basis_spec(n_max, l_max)
+    seen = set()
     for col, sp in enumerate(spec):
         if sp[0] != "3":
             continue
-        (n1, l1), (n2, l2), (n3, l3) = [divmod(p, 4) for p in sp[1:]]
+        (n1, l1), (n2, l2), (n3, l3) = [divmod(p, l_max + 1) for p in sp[1:]]
+        seen.add(tuple(sorted((l1, l2, l3))))
         R = [g @ prm.W[l, n] for n, l in ((n1, l1), (n2, l2), (n3, l3))]
         ref = R[0] * R[1] * R[2] / 6.0 ** 3 * (2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) \
             / (4 * np.pi) ** 2 * _w3j000(l1, l2, l3) ** 2
         assert B[col] == pytest.approx(ref, rel=1e-9, abs=1e-16), sp
+    if l_max == 4:  # every degree triple with an l = 4 block is reached
+        assert {(0, 4, 4), (1, 3, 4), (2, 2, 4), (2, 4, 4), (3, 3, 4), (4, 4, 4)} <= seen
+
+
+def test_gaunt_l4_entries_from_a_rotated_single_neighbour():
+    """The single-neighbour sum of a (l1, l2, 4) block over random directions: a wrong m != 0
+    entry of the l = 4 Gaunt tables makes sum_m G Y Y Y depend on the direction."""
+    G = ace.gaunt(4)
+    rng = np.random.default_rng(12)
+    dirs = rng.normal(size=(6, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    for (l1, l2, l3), g in G.items():
+        if 4 not in (l1, l2, l3):
+            continue
+        ref = (2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4 * np.pi) ** 2 * _w3j000(l1, l2, l3) ** 2
+        for u in dirs:
+            Y = ace.real_sph_harm(torch.as_tensor(u[None, :]), 4).numpy()[0]
+            ys = [Y[l * l:(l + 1) ** 2] for l in (l1, l2, l3)]
+            val = np.einsum("abc,a,b,c->", g, ys[0], ys[1], ys[2])
+            assert val == pytest.approx(ref, rel=1e-12, abs=1e-14), (l1, l2, l3)
 
 
 def test_perfect_fcc_only_cubic_invariants_survive():
@@ -237,9 +265,10 @@ def _cluster(seed=4):
     return synth.System(pos, np.full(3, -60.0), np.full(3, 60.0), (0, 0, 0))
 
 
-def test_invariance_rotation_translation_permutation():
+@pytest.mark.parametrize("nl", [(8, 3), (10, 4)])
+def test_invariance_rotation_translation_permutation(nl):
     s = _cluster()
-    prm = _ace(8, 3)
+    prm = _ace(*nl)
     eam_p = synth.eam_cu_like()
     w = np.random.default_rng(1).uniform(0, 1, s.n)
     ev = hybrid.evaluate(s, eam_p, prm, w)
