@@ -33,7 +33,9 @@ from cluster_util import Cutter
 pytestmark = pytest.mark.gpu
 
 FTOL = 1e-10        # eV/A, float64 library vs oracle
-BUDGET = 1e-2       # eV/A, float32 ACE vs the float64 oracle
+BUDGET = 1e-2       # eV/A, float32 ACE vs the float64 oracle: the stated budget
+TIGHT32 = 1e-5      # eV/A, the float32 path's rounding bound (accumulated float32 rounding
+                    # over O(1e4) terms per atom stays near 1e-6 eV/A)
 R_CLUSTER = 10.5    # A: forces on the centre need the densities of neighbours within r_c
 MAX_NB = 80
 
@@ -134,16 +136,17 @@ def _check_workload(ops, ctx, s, prec, ace_prm, seed, indenter=None):
         d32 = np.max(np.abs(f32[:, i] - ev["f_ace"][:, c]))
         worst32 = max(worst32, d32)
         assert d32 < BUDGET, (i, d32)
+        assert d32 < TIGHT32, (i, d32)
         if w[i] > 0:
             assert abs(e64[i] - ev["e_ace"][c]) < FTOL, i
-            assert abs(e32[i] - ev["e_ace"][c]) < 1e-3, i
+            assert abs(e32[i] - ev["e_ace"][c]) < TIGHT32, i
         # the integrator's total force at step 0 (float32 ACE, indenter included)
         f_ref = ev["f_eam"][:, c] + ev["f_ace"][:, c]
         if indenter is not None:
             fi, _ = verlet.indenter(s.pos[:, i:i + 1], s.lo, s.hi, s.periodic, np.asarray(indenter["center"]),
                                     indenter["radius"], indenter["k"])
             f_ref = f_ref + fi[:, 0]
-        assert np.max(np.abs(fmd[:, i] - f_ref)) < BUDGET, i
+        assert np.max(np.abs(fmd[:, i] - f_ref)) < TIGHT32, i
     print(f"{smp.size} sampled atoms; float32 ACE force error max {worst32 * 1e3:.5f} meV/A", flush=True)
 
 

@@ -19,6 +19,13 @@ from oracle import geometry, hybrid, precision, verlet
 pytestmark = pytest.mark.gpu
 
 FTOL = 1e-10
+# Rounding bounds of the float32 ACE path against the float64 one.  Each force component
+# sums O(1e4) float32 products per atom (unit roundoff 6e-8) over values of O(1) eV/A,
+# so accumulated rounding stays near 1e-6 eV/A; 1e-5 eV/A leaves an order of margin
+# while a dropped coupling entry or a misplaced adjoint column (O(1e-4..1e-2) eV/A with
+# coefficients of 0.01) exceeds it.  The 10 meV/A budget stays the reported bound.
+TIGHT32_F = 1e-5
+TIGHT32_E = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -227,8 +234,9 @@ def test_ace_fp32_error_budget(ops_ctx, case):
     df = (o32["f"] - o64["f"]).abs().max().item()
     de = (o32["e_site"] - o64["e_site"]).abs().max().item()
     print(f"fp32 vs fp64: max|dF| = {df * 1e3:.5f} meV/A, max|dE_i| = {de * 1e3:.5f} meV")
-    assert df < 1e-2
-    assert de < 1e-3
+    assert df < 1e-2  # the stated budget
+    assert df < TIGHT32_F, "float32 force error above its rounding bound"
+    assert de < TIGHT32_E, "float32 site-energy error above its rounding bound"
 
 
 @pytest.mark.parametrize("case", list(ACE_CASES))
