@@ -248,6 +248,17 @@ apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const double* e_e
                      const double* e_ace, const double* f_eam, const double* f_ace,
                      double* e_site, double* f, double* e_pot);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): apx_blend with the same arguments,
+ * results and error behaviour, whose block partial sums live in a static device array
+ * of the library (65,536 doubles per GPU, held until the process ends) instead of the
+ * context's scratch.  It calls no allocation routine.  Limit: n <= 134,217,728 atoms
+ * (65,536 blocks of 2,048); larger n returns APX_EINVAL.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (different streams or contexts) race. */
+apx_status apx_blend_noalloc(apx_ctx* ctx, int64_t n, const double* w, const double* e_eam,
+                             const double* e_ace, const double* f_eam, const double* f_ace,
+                             double* e_site, double* f, double* e_pot);
+
 /* ---------------------------------------------------------- integration */
 #define APX_MODE_ADAPTIVE 0 /* EAM everywhere, ACE where w > 0, w from the criterion */
 #define APX_MODE_FULL_ACE 1 /* w = 1 for every mobile atom, no EAM, no detection */

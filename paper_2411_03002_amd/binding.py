@@ -103,6 +103,7 @@ PROTOTYPES = {
     "apx_ace_energy_forces": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), _P, _P, _P, C.c_int64,
                                           C.c_int32, _P, _P, _P, _P]),
     "apx_blend": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "apx_blend_noalloc": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "apx_md_create": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(MdParams), C.POINTER(EamParams), _P,
                                   C.POINTER(PrecParams), C.POINTER(_P)]),
     "apx_md_destroy": (None, [_P]),

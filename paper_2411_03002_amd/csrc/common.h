@@ -108,6 +108,10 @@ apx_status bin_atoms(apx_ctx* ctx, const apx_atoms* a, const Grid& g);
 // Exclusive scan of m int32 values `in` into `out` (m+1 entries, out[m] = total).
 apx_status scan_exclusive(apx_ctx* ctx, const int* in, long long m, int* out);
 
+// Resolves the per-device address of the blend's static scratch array (blend.hip); called
+// by apx_ctx_create with the context's device current.
+apx_status blend_scratch_setup(apx_ctx* ctx);
+
 // Reads `count` ints from device memory into host memory (synchronising).
 apx_status read_ints(apx_ctx* ctx, const int* dev, int* host, int count);
 

@@ -293,6 +293,11 @@ apx_status apx_ctx_create(int32_t device, void* stream, apx_ctx** out) {
     delete c;
     return APX_ENOMEM;
   }
+  if (blend_scratch_setup(c) != APX_OK) {
+    (void)hipHostFree(c->host_pinned);
+    delete c;
+    return APX_EDEVICE;
+  }
   *out = c;
   return APX_OK;
 }

@@ -333,15 +333,18 @@ def ace_energy_forces(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, model:
     return out
 
 
-def blend(ctx: Context, w, e_eam, e_ace, f_eam, f_ace) -> dict:
+def blend(ctx: Context, w, e_eam, e_ace, f_eam, f_ace, out=None, noalloc: bool = False) -> dict:
+    """apx_blend, or apx_blend_noalloc with ``noalloc``; ``out`` supplies the output tensors."""
     ctx.bind_stream()
     n = int(e_eam.numel())
     dev = e_eam.device
-    out = dict(e_site=torch.empty(n, dtype=torch.float64, device=dev),
-               f=torch.empty((3, n), dtype=torch.float64, device=dev),
-               e_pot=torch.empty(1, dtype=torch.float64, device=dev))
-    ctx._check(ctx.lib.apx_blend(ctx.h, n, _p(w), _p(e_eam), _p(e_ace), _p(f_eam), _p(f_ace),
-                                 _p(out["e_site"]), _p(out["f"]), _p(out["e_pot"])))
+    if out is None:
+        out = dict(e_site=torch.empty(n, dtype=torch.float64, device=dev),
+                   f=torch.empty((3, n), dtype=torch.float64, device=dev),
+                   e_pot=torch.empty(1, dtype=torch.float64, device=dev))
+    fn = ctx.lib.apx_blend_noalloc if noalloc else ctx.lib.apx_blend
+    ctx._check(fn(ctx.h, n, _p(w), _p(e_eam), _p(e_ace), _p(f_eam), _p(f_ace),
+                  _p(out["e_site"]), _p(out["f"]), _p(out["e_pot"])))
     return out
 
 
