@@ -13,14 +13,22 @@ Appendix D, "Centro-symmetry parameter" and "Switching function"):
 * eq. lambda_4_i: minimum step size.  The new mean replaces the previous filtered value
   only if it differs from it by at least dw_min, or if it is exactly 0 or 1; otherwise
   the previous filtered value is kept.
-* eq. vv, step 2: the new weight is a function of the previous weight state and of the
-  positions at the new time, so the newest sample of each mean is the one taken at the
-  positions of the call.
+Two readings of the windows, selected by ``window``:
+* "past" (the default; eqs. csp_2_i and lambda_3_i as printed, sums over n = 1..N of
+  samples at t - n dt): the mean of CSP that forms lambda_0 at time t holds the samples
+  taken before t, not the one taken at t; the weight used by the force evaluations after
+  a sample is the filtered mean of the spread weights up to and including that sample.
+  The force routine's order of Appendix G (fast potential, precise potential, CSP, then
+  lambda) fits this reading: the forces of step t use the weight formed before t, and the
+  CSP and lambda samples of step t serve the steps after it.
+* "current": the newest sample enters both means (eq. vv step 2 read as forming the weight
+  of step t from the positions of step t before its forces).
+With "past", the first call has no earlier CSP sample and averages the current one.
 
 Readings (the paper is silent on these):
 * One call takes one sample.  A caller that updates the weights every k steps samples
   every k steps, and N then counts samples, not steps.
-* Before N samples exist, a mean is over the samples taken so far.
+* Before N samples exist, a mean is over the samples available.
 * The first call has no previous filtered value: the filtered weight is the mean.
 * Both means use the same N (the paper sets N_lambda,avg = N_CSP,avg).
 * In the precise-weight form 1 - mean(lambda) = mean(1 - lambda) and the filter's tests
@@ -63,9 +71,12 @@ def min_step_filter(w_avg, w_prev, dw_min):
 class TimeAveragedSwitch:
     """Per-atom history of CSP and w_min samples and the filtered weight."""
 
-    def __init__(self, n_avg: int, dw_min: float):
+    def __init__(self, n_avg: int, dw_min: float, window: str = "past"):
         if n_avg < 1:
             raise ValueError("n_avg must be at least 1")
+        if window not in ("past", "current"):
+            raise ValueError(window)
+        self.window = window
         self.n_avg = int(n_avg)
         self.dw_min = float(dw_min)
         self.csp_hist = []  # newest first
@@ -80,8 +91,12 @@ class TimeAveragedSwitch:
         if csp is None:
             csp = precision.csp(system.pos, system.lo, system.hi, system.periodic, csr, r_cut=params.r_cut,
                                 n_nn=params.n_nn, n_buffer=params.n_buffer, frozen=fz)
-        self.csp_hist = ([np.asarray(csp, dtype=np.float64)] + self.csp_hist)[:self.n_avg]
-        csp_avg = moving_average(self.csp_hist)
+        csp = np.asarray(csp, dtype=np.float64)
+        if self.window == "past" and self.csp_hist:
+            csp_avg = moving_average(self.csp_hist)  # the samples before this one
+        else:
+            csp_avg = moving_average(([csp] + self.csp_hist)[:self.n_avg])
+        self.csp_hist = ([csp] + self.csp_hist)[:self.n_avg]
         w0 = precision.w0_from_csp(csp_avg, params.csp_lo, params.csp_hi, params.switch_kind, fz)
         if w0_extra is not None:
             w0 = np.maximum(w0, w0_extra)

@@ -11,6 +11,14 @@ log(|F_ACE - F_EAM| + 1e-3) and the loss is the mean squared error over a batch.
 Adam: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + 1e-8).
 BF16 inference: weights and every layer input rounded to bfloat16 (nearest-even),
 products summed in float32, tanh in float32.
+
+Detection weight of the learned criterion (Appendix B: eq. lambda_1_i with its argument
+replaced; the argument must be 0 for atoms that need the precise potential and 1 for the
+others).  The network predicts y = log(|dF| + 1e-3), so the predicted force gap is
+exp(y) - 1e-3 and, in the precise-weight form,
+    w0 = 1 - f_cut((exp(y) - 1e-3 - tau_lo) / (tau_hi - tau_lo))
+with f_cut of Appendix B; an atom with any feature outside the range seen in training
+gets 0 here and keeps the centro-symmetry weight alone (the criterion's fallback).
 """
 
 from __future__ import annotations
@@ -18,6 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 from .geometry import displacements, sq_dist
+from .precision import f_cut
 
 LAYERS = (4, 64, 64, 64, 1)
 COORD_R = 3.08
@@ -107,3 +116,18 @@ def forward_bf16(params, x):
         h = to_bf16(h)
     W = to_bf16(params[6]).astype(np.float32)
     return (h.astype(np.float32) @ W.T + np.float32(params[7]))[:, 0].astype(np.float32)
+
+
+def learned_w0(pred, feat, fmin, fmax, tau_lo, tau_hi):
+    """Precise weight from predictions ``pred`` [n] (float32 log force gaps) and features
+    ``feat`` [n, 4] (float32): the predicted gap exp(pred) - 1e-3 (float64) switched by
+    1 - f_cut((gap - tau_lo) / (tau_hi - tau_lo)); 0 where a feature lies outside
+    [fmin, fmax] (float32 bounds, inclusive)."""
+    pred = np.asarray(pred, dtype=np.float32).astype(np.float64)
+    feat = np.asarray(feat, dtype=np.float32)
+    fmin = np.asarray(fmin, dtype=np.float32)
+    fmax = np.asarray(fmax, dtype=np.float32)
+    inside = np.all((feat >= fmin[None, :]) & (feat <= fmax[None, :]), axis=1)
+    gap = np.exp(pred) - 1e-3
+    w = 1.0 - f_cut((gap - tau_lo) / (tau_hi - tau_lo))
+    return np.where(inside, w, 0.0)

@@ -5,6 +5,15 @@ One step of length dt (Sec. II C 1):
   2. w(t + dt) recomputed from x(t + dt) (every ``precision_every`` steps; never if 0)
   3. a(t + dt) = F(t + dt) / m with the new weights (plus the external indenter force)
   4. v(t + dt) = v(t + dt/2) + a(t + dt) dt / 2
+Time-averaged weights (``avg``; Appendix B) take one sample per update.  With the "past"
+window the sample of step t is taken after that step's forces (the force routine's order
+fast potential, precise potential, CSP, lambda of Appendix G), and the weight it forms is
+used from step t + 1 on; with the "current" window and with instantaneous weights the
+update precedes the forces, as in step 2 above.
+The local thermostat (``thermostat``; Sec. II C 2, Appendix C) runs at the end of every
+step whose force evaluation uses weights different from the previous one: the forces of
+both weight sets at x(t + dt) give the energy errors, and the momenta are rescaled
+(``oracle.thermostat``).
 Frozen atoms are never moved.  Periodic coordinates are wrapped into [lo, hi) after the
 drift.  The indenter is a repulsive sphere of radius R: U = (K/3)(R - d)^3 and force
 K (R - d)^2 along the outward unit vector, for centre distance d < R (external field,
@@ -16,8 +25,10 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import averaging as _avg
 from . import hybrid as _hyb
 from . import precision as _prec
+from . import thermostat as _thermo
 from .geometry import neighbor_csr, min_image
 
 MASS_CU = 63.546  # amu
@@ -53,42 +64,75 @@ def kinetic(v, mass=MASS_CU):
 
 
 def run(system, eam_p, ace_p, prec_p, dt, n_steps, precision_every=0, w=None,
-        indent=None, mass=MASS_CU):
-    """Integrate ``n_steps``; returns dict(x, v, w, f, e_pot, e_kin per step incl. t=0)."""
+        indent=None, mass=MASS_CU, avg=None, thermostat=None):
+    """Integrate ``n_steps``; returns dict(x, v, w, f, e_pot, e_kin per step incl. t=0, and
+    per step the thermostat's record).
+
+    ``avg``: dict(n_avg, dw_min, window) for time-averaged weights; ``thermostat``:
+    dict(r_omega, omega_max, seed)."""
     s = system.copy()
     x = s.pos.copy()
     v = np.zeros_like(x) if s.vel is None else s.vel.copy()
     mobile = np.ones(s.n, bool) if s.frozen is None else ~s.frozen.astype(bool)
     rc = max(eam_p.rc, ace_p.rc if ace_p is not None else 0.0)
+    tas = None
+    if avg is not None:
+        tas = _avg.TimeAveragedSwitch(avg["n_avg"], avg["dw_min"], avg.get("window", "past"))
+    after_forces = tas is not None and tas.window == "past"
 
-    def forces(xx, ww, t):
+    def evaluate(xx, ww):
         s.pos = xx
-        ev = _hyb.evaluate(s, eam_p, ace_p, ww)
-        f = ev["f"]
-        if indent is not None:
-            c = np.asarray(indent["center"]) + t * np.asarray(indent["velocity"])
-            fi, _ = indenter(xx, s.lo, s.hi, s.periodic, c, indent["radius"], indent["k"])
-            f = f + fi
-        return f, ev["e_pot"]
+        return _hyb.evaluate(s, eam_p, ace_p, ww)
+
+    def external(xx, t):
+        if indent is None:
+            return 0.0
+        c = np.asarray(indent["center"]) + t * np.asarray(indent["velocity"])
+        return indenter(xx, s.lo, s.hi, s.periodic, c, indent["radius"], indent["k"])[0]
 
     def weights(xx):
         s.pos = xx
         csr = neighbor_csr(xx, s.lo, s.hi, s.periodic, rc)
+        if tas is not None:
+            return tas.update(s, prec_p, csr)["w"]
         return _prec.compute_precision(s, prec_p, csr)["w"]
 
     if w is None:
         w = weights(x) if prec_p is not None else np.zeros(s.n)
-    f, ep = forces(x, w, 0.0)
-    e_pot, e_kin = [ep], [kinetic(v[:, mobile], mass)]
+    ev = evaluate(x, w)
+    f = ev["f"] + external(x, 0.0)
+    e_pot, e_kin, records = [ev["e_pot"]], [kinetic(v[:, mobile], mass)], []
     c = 0.5 * dt * EV_PER_AMU_A2_PS2 / mass
+    w_used = w  # weights of the last force evaluation
     for step in range(1, n_steps + 1):
         v[:, mobile] += c * f[:, mobile]
         x[:, mobile] += dt * v[:, mobile]
         x = wrap_positions(x, s.lo, s.hi, s.periodic)
-        if precision_every and step % precision_every == 0:
+        due = bool(precision_every) and step % precision_every == 0
+        if due and not after_forces:
             w = weights(x)
-        f, ep = forces(x, w, step * dt)
+        ev = evaluate(x, w)
+        v_half = v.copy()
+        f = ev["f"] + external(x, step * dt)
         v[:, mobile] += c * f[:, mobile]
-        e_pot.append(ep)
+        rec = None
+        if thermostat is not None and np.any(w != w_used):
+            ec = evaluate(x, w_used)
+            e_prec = np.where(w > 0.0, ev["e_ace"], ec["e_ace"])
+            dE, _, _ = _thermo.energy_errors(w_used, w, ev["e_eam"], e_prec, ec["f"], ev["f"], v_half, dt, mass,
+                                             mobile)
+            s.pos = x
+            rec = _thermo.correct(x, s.lo, s.hi, s.periodic, v, dE, mobile, mass, thermostat["r_omega"],
+                                  thermostat["omega_max"], thermostat["seed"], step)
+            rec["dE"] = dE
+            rec["e_pot_ref"] = ec["e_pot"]  # the constant-weight reference at this step
+            v_ref = v_half + c * (ec["f"] + external(x, step * dt))
+            rec["e_kin_ref"] = kinetic(v_ref[:, mobile], mass)
+        records.append(rec)
+        w_used = w
+        if due and after_forces:
+            w = weights(x)
+        e_pot.append(ev["e_pot"])
         e_kin.append(kinetic(v[:, mobile], mass))
-    return dict(x=x, v=v, w=w, f=f, e_pot=np.array(e_pot), e_kin=np.array(e_kin))
+    return dict(x=x, v=v, w=w, w_used=w_used, f=f, e_pot=np.array(e_pot), e_kin=np.array(e_kin),
+                thermostat=records)
