@@ -39,6 +39,7 @@ typedef int32_t apx_status;
 #define APX_EDEVICE (-3)    /* a HIP runtime call failed */
 #define APX_ECAPACITY (-4)  /* a caller buffer is too small; the needed size is returned */
 #define APX_ENONFINITE (-5) /* a non-finite value where a finite one is required */
+#define APX_ERADICAND (-6)  /* a thermostat correction had a negative radicand and was skipped */
 
 #define APX_FP64 0
 #define APX_FP32 1
@@ -112,18 +113,22 @@ typedef struct {
   int32_t n_nn;        /* N, even, 2..16 (12 for FCC) */
   int32_t n_buffer;    /* N_buffer, N + N_buffer <= 16 */
   int32_t switch_kind; /* 0 linear, 1 f_cut */
-  int32_t flags;       /* APX_PREC_CSP_GIVEN: csp is an input, the CSP pass is skipped */
+  int32_t flags;       /* APX_PREC_CSP_GIVEN: csp is an input, the CSP pass is skipped;
+                          APX_PREC_EXTRA_LOCAL: w0_extra joins after the spreading */
   double csp_lo, csp_hi; /* Angstrom^2 */
   double r_cut;          /* CSP candidate cutoff, <= nl->r_list */
   double r_lo, r_hi;     /* spreading radii, Angstrom */
 } apx_prec_params;
 
 #define APX_PREC_CSP_GIVEN 1
+#define APX_PREC_EXTRA_LOCAL 2
 
 /* Outputs (device, length n): csp, w0, w, mask (1 where w > 0); active receives the
  * indices with w > 0 in ascending order and *n_active (host, (sync)) their number.
- * w0_extra (device [n] or NULL) is an additional detection weight combined with the
- * CSP-based w0 by max before spreading (used by the learned criterion). */
+ * w0_extra (device [n] or NULL) is an additional detection weight (the learned
+ * criterion's) combined by max with the CSP-based w0 before spreading, or, with
+ * APX_PREC_EXTRA_LOCAL, with the spread weight after it (its detections are then not
+ * spread; w0 is the CSP-based weight alone).  Frozen atoms keep 0 either way. */
 apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
                                  const apx_prec_params* p, const double* w0_extra,
                                  double* csp, double* w0, double* w, uint8_t* mask,
@@ -134,10 +139,15 @@ apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx
  * precise-weight form w = 1 - lambda.  One call takes one sample at the given positions:
  *   csp      the instantaneous CSP (as apx_compute_precision; an input with
  *            APX_PREC_CSP_GIVEN), pushed into csp_ring;
- *   csp_avg  the mean of the newest min(samples + 1, n_avg) CSP samples;
+ *   csp_avg  window APX_WINDOW_PAST (eq. csp_2_i as printed, a sum over n = 1..N of
+ *            earlier samples): the mean of the min(samples, n_avg) CSP samples taken
+ *            before this call (this call's sample alone on the first call);
+ *            APX_WINDOW_CURRENT: the mean of the newest min(samples + 1, n_avg) samples,
+ *            this call's included;
  *   w0       the switch of csp_avg, combined with w0_extra by max; frozen atoms 0;
  *   w_min    w0 spread as in apx_compute_precision, pushed into w_ring;
- *   w_avg    (nullable) the mean of the newest w_min samples;
+ *   w_avg    (nullable) the mean of the newest min(samples + 1, n_avg) w_min samples
+ *            (eq. lambda_3_i: the weight for the force evaluations after this sample);
  *   w        in: the filtered weight returned by the previous call (ignored on the
  *            first); out: w_avg where |w_avg - w_prev| >= dw_min or w_avg is 0 or 1,
  *            else w_prev (on the first call w_avg);
@@ -147,10 +157,13 @@ apx_status apx_compute_precision(apx_ctx* ctx, const apx_atoms* atoms, const apx
  * `samples` counts the samples taken (0 before the first call) and each successful call
  * advances it by one; the ring slot of a call is samples % n_avg.  All arrays are device
  * arrays of length n.  EINVAL: n_avg outside 1..4096, samples < 0, dw_min < 0 or NaN,
- * missing rings, csp_avg or w_min, or any condition of apx_compute_precision. */
+ * an unknown window, missing rings, csp_avg or w_min, or any condition of
+ * apx_compute_precision. */
+#define APX_WINDOW_PAST 0
+#define APX_WINDOW_CURRENT 1
 typedef struct {
   int32_t n_avg;      /* samples per moving mean */
-  int32_t reserved;
+  int32_t window;     /* APX_WINDOW_PAST or APX_WINDOW_CURRENT */
   int64_t samples;    /* samples taken so far */
   double dw_min;      /* minimum step of the filtered weight */
   double* csp_ring;   /* device [n_avg][n] */
@@ -165,10 +178,10 @@ apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* atoms, const
 
 /* ------------------------------------------------------------------- EAM */
 /* Sec. III B eq. energy_eam: E_i = F(rho_i) + 1/2 sum_j phi(r_ij), rho_i = sum_j rho(r_ij)
- * over r_ij < r_cut, psi(x) = x^4/(1 + x^4) for x < 0 else 0 (the taper of Appendix D).
+ * over r_ij < r_cut, psi(x) = x^4/(1 + x^4) for x < 0 else 0 (the taper of Appendix E).
  * kind APX_EAM_CLOSED: phi(r) = A exp(-alpha(r - r0)) psi((r - r_cut)/h),
  *     rho(r) = exp(-beta(r - r0)) psi((r - r_cut)/h), F(rho) = -sqrt(rho).
- * kind APX_EAM2: the paper's EAM2 copper potential (Appendix D, parameters of Table II;
+ * kind APX_EAM2: the paper's EAM2 copper potential (Appendix E, parameters of Table III;
  *     the refit's offset of Sec. III B added to the embedding), eam2[] holding in order
  *     E1, E2, delta, alpha1, alpha2, r01, r02, S1, S2, S3, rs1, rs2, rs3, a, beta1, beta2,
  *     r03, r04, xi0, xi2, q1, q2, q3, q4, Q1, Q2, f0:
@@ -248,6 +261,11 @@ apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const double* e_e
                      const double* e_ace, const double* f_eam, const double* f_ace,
                      double* e_site, double* f, double* e_pot);
 
+/* *out (device scalar) = sum_i w_i e_i over n atoms (w NULL: all 1), summed in the blend's
+ * deterministic pairwise order: the weighted precise energy sum_i w_i E_i^ACE of the
+ * site-weighted energy (Sec. II A eq. energy_hyb), used as the autograd forward value. */
+apx_status apx_weighted_sum(apx_ctx* ctx, int64_t n, const double* w, const double* e, double* out);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): apx_blend with the same arguments,
  * results and error behaviour, whose block partial sums live in a static device array
@@ -263,6 +281,49 @@ apx_status apx_blend_noalloc(apx_ctx* ctx, int64_t n, const double* w, const dou
 #define APX_MODE_ADAPTIVE 0 /* EAM everywhere, ACE where w > 0, w from the criterion */
 #define APX_MODE_FULL_ACE 1 /* w = 1 for every mobile atom, no EAM, no detection */
 #define APX_MODE_EAM 2      /* w = 0, no ACE, no detection */
+
+/* ------------------------------------------------------- local thermostat */
+/* Energy correction of a weight update (Sec. II C 2; Appendix C), precise-weight form
+ * w = 1 - lambda.  Energy errors, eqs. Delta_V_i, Delta_T_i, Delta_E_i, per atom:
+ *   dV_i = (w_d_i - w_c_i)(e_fast_i - e_precise_i)   (0 where w_d_i == w_c_i),
+ *   dT_i = sum_a [dt^2/(8m)((F^c_ia)^2 - (F^d_ia)^2) + (F^c_ia - F^d_ia) v_half_ia dt/2],
+ *   dE_i = dV_i + dT_i (0 for frozen atoms),
+ * with F^d = f_d, F^c = f_d + df (interatomic forces only, eV/A; [3][n]), v_half the
+ * velocities after the first half kick (A/ps, [3][n]), m = mass/9648.5332 (mass in amu),
+ * dt in ps.  w_c: the constant reference weights (those of the previous force
+ * evaluation); w_d: the updated ones.  frozen may be NULL.  Output dE [n] (eV). */
+apx_status apx_thermostat_energy_errors(apx_ctx* ctx, int64_t n, const uint8_t* frozen, const double* w_c,
+                                        const double* w_d, const double* e_fast, const double* e_precise,
+                                        const double* f_d, const double* df, const double* v_half, double dt,
+                                        double mass, double* dE);
+
+/* Correction, eqs. p_resc_omega and beta_omega_i: every mobile atom i with dE_i != 0
+ * rescales the velocities of its group Omega_i about the group's centre-of-mass velocity
+ * v_cm by beta = sqrt(dE_i / K_rel + 1), K_rel = sum_j m |v_j - v_cm|^2 / 2, which keeps
+ * the group's momentum and changes its kinetic energy by dE_i.  Omega_i is atom i plus the
+ * mobile atoms j != i with minimum-image r_ij^2 < r_omega^2 at the given positions, all of
+ * them if there are fewer than omega_max, else the omega_max - 1 with the smallest
+ * priority: the first word of Philox4x64-10 (Salmon et al., SC'11) with counter
+ * (i, j, step, 0) and key (seed, 0), ties to the smaller j.  Corrections run one after the
+ * other in the order (colour, atom index), the colour being the parity pattern of the
+ * atom's cell in a grid of floor(L/(2 r_omega)) cells per axis (at least 1; one fewer if
+ * odd on a periodic axis), cell floor((x - lo) * (nc / L)) clamped; atoms of one colour in
+ * different cells are 2 r_omega apart, so their groups are disjoint.  vel [3][n] (A/ps) is
+ * updated in place.  *n_corrected and *n_failed (host, (sync)) count the corrections made
+ * and those skipped because the radicand was negative or the group had no relative
+ * momentum; any skip returns APX_ERADICAND after the others are applied (the paper
+ * enlarges the group then, Appendix D).  APX_ECAPACITY: more than 8192 corrections in one
+ * colour cell or more than 4096 candidates within r_omega of one atom (reduce r_omega). */
+typedef struct {
+  double r_omega;      /* group radius, A */
+  int32_t omega_max;   /* |Omega|, the largest group (Appendix F: 800) */
+  int32_t reserved;
+  uint64_t seed;       /* key of the group draw */
+} apx_thermo_params;
+
+apx_status apx_thermostat_correct(apx_ctx* ctx, const apx_atoms* atoms, double* vel, const double* dE,
+                                  const apx_thermo_params* p, int64_t step, double mass, int64_t* n_corrected,
+                                  int64_t* n_failed);
 
 typedef struct {
   double dt;               /* ps */
@@ -280,6 +341,14 @@ typedef struct {
   double ind_center[3];      /* centre at step 0 */
   double ind_velocity[3];    /* A/ps */
   double avg_dw_min;         /* minimum step of the time-averaged weight */
+  int32_t avg_window;        /* APX_WINDOW_PAST: the sample of an update step is taken after
+                                that step's forces (the force routine's order of Appendix G:
+                                fast potential, precise potential, CSP, lambda) and its
+                                weight serves the following steps; APX_WINDOW_CURRENT: the
+                                update precedes the step's forces (eq. vv step 2) */
+  int32_t thermostat;        /* 1: local thermostat at every step whose weights differ from
+                                the previous force evaluation's (apx_thermostat_*) */
+  apx_thermo_params thermo;  /* group radius, size and draw key of the thermostat */
 } apx_md_params;
 
 typedef struct {
@@ -290,6 +359,9 @@ typedef struct {
   double e_pot, e_kin;   /* at the end of the call, eV (potential excludes the indenter) */
   double e_indenter;     /* indenter energy at the end, eV */
   int64_t ace_atoms;     /* sum over the call's steps of the atoms ACE was evaluated for */
+  int64_t thermo_steps;      /* steps whose weights changed and were corrected */
+  int64_t thermo_corrected;  /* corrections applied */
+  int64_t thermo_failed;     /* corrections skipped (negative radicand) */
 } apx_md_stats;
 
 /* An integrator bound to a box, potentials and criterion.  `atoms` supplies n, box,
@@ -302,8 +374,14 @@ void apx_md_destroy(apx_md* md);
 /* Neighbour list, weights (unless mode fixes them) and forces at the current
  * positions: pos[3][n] (in), f[3][n] (out), w[n] (out). */
 apx_status apx_md_init(apx_md* md, const double* pos, double* f, double* w);
-/* Sec. II C eq. vv: n_steps velocity-Verlet steps with the weight update as step 2.
- * pos, vel (A/ps), f, w are device arrays updated in place. stats: host, (sync). */
+/* Sec. II C eq. vv: n_steps velocity-Verlet steps with the weight update as step 2 (or,
+ * with time-averaged weights and APX_WINDOW_PAST, after the step's forces).  pos, vel
+ * (A/ps), f, w are device arrays updated in place; w holds the weights of the next force
+ * evaluation.  With the thermostat on, a step whose weights changed evaluates the forces of
+ * both weight sets in one pass (the difference only where weights differ; ACE over the
+ * atoms with either weight > 0), then corrects the velocities after the second half kick.
+ * A skipped correction ends the call after its step with APX_ERADICAND (stats filled).
+ * stats: host, (sync). */
 apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, double* f, double* w,
                            int64_t n_steps, apx_md_stats* stats);
 /* Switches the integrator's detection to the learned criterion combined with the
@@ -349,9 +427,24 @@ apx_status apx_mlp_train_step(apx_ctx* ctx, apx_mlp* m, const float* feat, const
                               const int32_t* sel, int64_t nb, float lr, float* loss);
 /* Inference with bfloat16 weights and activations on the matrix cores, float32 sums. */
 apx_status apx_mlp_infer_bf16(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, float* out);
-/* pred [n] = bfloat16 inference; w0_extra [n] = 1 - f_cut((exp(pred) - 1e-3 - tau_lo) /
- * (tau_hi - tau_lo)) for atoms inside the training feature range, 0 outside (those keep
- * the centro-symmetry weight alone when combined by apx_compute_precision). */
+/* Training labels of the learned criterion from the two potentials' forces f_precise,
+ * f_fast [3][n] (float64, eV/A): dF [n] (float64, nullable) = |f_precise - f_fast| and
+ * label [n] (float32) = log(dF + 1e-3). */
+apx_status apx_mlp_labels(apx_ctx* ctx, int64_t n, const double* f_precise, const double* f_fast, double* dF,
+                          float* label);
+/* Statistics of the features feat [n][4] (float32), n >= 1: stats [16] (device, float64) =
+ * per column the mean [0..3], the standard deviation with n - 1 [4..7] (the input
+ * standardisation), the minimum [8..11] and the maximum [12..15] (the training range). */
+apx_status apx_mlp_feature_stats(apx_ctx* ctx, const float* feat, int64_t n, double* stats);
+/* Detection weight of the learned criterion (Appendix B: the argument of eq. lambda_1_i
+ * replaced by the predicted force gap) from given predictions pred [n] (float32,
+ * log(|dF| + 1e-3)) and features feat [n][4]: w0_extra [n] = 1 - f_cut((exp(pred) - 1e-3 -
+ * tau_lo) / (tau_hi - tau_lo)) (exp in float64) for atoms whose features all lie in the
+ * training range [fmin, fmax] (inclusive; apx_mlp_set_range), 0 outside (those keep the
+ * centro-symmetry weight alone when combined by apx_compute_precision). */
+apx_status apx_mlp_weight(apx_ctx* ctx, const apx_mlp* m, const float* pred, const float* feat, int64_t n,
+                          double tau_lo, double tau_hi, double* w0_extra);
+/* pred [n] = bfloat16 inference, then w0_extra [n] as apx_mlp_weight. */
 apx_status apx_mlp_precision(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, double tau_lo,
                              double tau_hi, float* pred, double* w0_extra);
 

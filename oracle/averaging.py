@@ -1,7 +1,7 @@
 """Time-averaged switching (oracle; test infrastructure only, never called by the library).
 
 Paper passages (Appendix B, "Construction of the switching function"; parameters in
-Appendix D, "Centro-symmetry parameter" and "Switching function"):
+Appendix F, "Centro-symmetry parameter" and "Switching function", Table IV):
 * eq. csp_2_i: the centro-symmetry parameter entering the switch is the mean of the
   last N_CSP,avg samples of CSP_i.
 * eq. lambda_1_i: the switch is applied to that mean (here in the precise-weight form
@@ -98,11 +98,12 @@ class TimeAveragedSwitch:
             csp_avg = moving_average(([csp] + self.csp_hist)[:self.n_avg])
         self.csp_hist = ([csp] + self.csp_hist)[:self.n_avg]
         w0 = precision.w0_from_csp(csp_avg, params.csp_lo, params.csp_hi, params.switch_kind, fz)
-        if w0_extra is not None:
-            w0 = np.maximum(w0, w0_extra)
-            if fz is not None:
-                w0 = np.where(fz.astype(bool), 0.0, w0)
+        local = getattr(params, "extra_local", False)
+        if w0_extra is not None and not local:
+            w0 = precision.combine_extra(w0, w0_extra, fz)
         w_min = precision.spread(system.pos, system.lo, system.hi, system.periodic, w0, params.r_lo, params.r_hi, fz)
+        if w0_extra is not None and local:
+            w_min = precision.combine_extra(w_min, w0_extra, fz)
         self.w_hist = ([w_min] + self.w_hist)[:self.n_avg]
         w_avg = moving_average(self.w_hist)
         self.w = min_step_filter(w_avg, self.w, self.dw_min)

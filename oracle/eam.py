@@ -3,13 +3,13 @@
 E_i = F(rho_i) + 1/2 sum_j phi(r_ij),  rho_i = sum_j rho(r_ij), over j != i with r_ij < r_c.
 
 Functional form of the synthetic fast potential (closed form; the taper psi is the one
-the paper uses for its EAM2 pair and density functions, Appendix D):
+the paper uses for its EAM2 pair and density functions, Appendix E):
     psi(x)   = x^4 / (1 + x^4) for x < 0, else 0
     phi(r)   = A exp(-alpha (r - r0)) psi((r - r_c)/h)
     rho(r)   = exp(-beta (r - r0)) psi((r - r_c)/h)
     F(rho)   = -sqrt(rho)   (F = 0 at rho = 0)
 
-The paper's own EAM2 copper potential (Appendix D; parameter objects with the field
+The paper's own EAM2 copper potential (Appendix E; parameter objects with the field
 ``xi0``) is the second form:
     Phi(r)  = (E1 M(r, r01, alpha1) + E2 M(r, r02, alpha2) + delta) psi((r - rc)/h)
               - sum_n Theta(rs_n - r) S_n (rs_n - r)^4,
@@ -39,13 +39,13 @@ def _is_eam2(p) -> bool:
 
 
 def _morse(r, r0, alpha):
-    """M(r, r0, alpha) of Appendix D: exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))."""
+    """M(r, r0, alpha) of Appendix E: exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))."""
     return torch.exp(-2.0 * alpha * (r - r0)) - 2.0 * torch.exp(-alpha * (r - r0))
 
 
 def pair_phi(r: torch.Tensor, p) -> torch.Tensor:
     if _is_eam2(p):
-        # Appendix D: (E1 M(r, r01, a1) + E2 M(r, r02, a2) + delta) psi((r - rc)/h)
+        # Appendix E: (E1 M(r, r01, a1) + E2 M(r, r02, a2) + delta) psi((r - rc)/h)
         #             - sum_n Theta(rs_n - r) S_n (rs_n - r)^4
         v = (p.E1 * _morse(r, p.r01, p.alpha1) + p.E2 * _morse(r, p.r02, p.alpha2) + p.delta) * psi((r - p.rc) / p.h)
         for S, rs in zip(p.S, p.rs):
@@ -56,14 +56,14 @@ def pair_phi(r: torch.Tensor, p) -> torch.Tensor:
 
 def pair_rho(r: torch.Tensor, p) -> torch.Tensor:
     if _is_eam2(p):
-        # Appendix D: (a exp(-beta1 (r - r03)^2) + exp(-beta2 (r - r04))) psi((r - rc)/h)
+        # Appendix E: (a exp(-beta1 (r - r03)^2) + exp(-beta2 (r - r04))) psi((r - rc)/h)
         return (p.a * torch.exp(-p.beta1 * (r - p.r03) ** 2) + torch.exp(-p.beta2 * (r - p.r04))) * psi((r - p.rc) / p.h)
     return torch.exp(-p.beta * (r - p.r0)) * psi((r - p.rc) / p.h)
 
 
 def embed(rho: torch.Tensor, p=None) -> torch.Tensor:
     if p is not None and _is_eam2(p):
-        # Appendix D eq. mishin_embedding_function, plus the fit's offset (Sec. III B)
+        # Appendix E eq. mishin_embedding_function, plus the fit's offset (Sec. III B)
         x = rho - 1.0
         low = p.xi0 + 0.5 * p.xi2 * x ** 2
         for k, qn in enumerate(p.q):

@@ -131,3 +131,21 @@ def learned_w0(pred, feat, fmin, fmax, tau_lo, tau_hi):
     gap = np.exp(pred) - 1e-3
     w = 1.0 - f_cut((gap - tau_lo) / (tau_hi - tau_lo))
     return np.where(inside, w, 0.0)
+
+
+def labels(f_precise, f_fast):
+    """Training target of the learned criterion: dF = |F^precise - F^fast| per atom
+    (float64, forces [3, n]) and log(dF + 1e-3) rounded to float32."""
+    d = np.asarray(f_precise, dtype=np.float64) - np.asarray(f_fast, dtype=np.float64)
+    dF = np.sqrt((d * d).sum(axis=0))
+    return dF, np.log(dF + 1e-3).astype(np.float32)
+
+
+def feature_stats(feat):
+    """Per-column mean, standard deviation with n - 1 degrees of freedom, minimum and
+    maximum of float32 features [n, 4], in float64: the input standardisation and the
+    training range of the criterion."""
+    x = np.asarray(feat, dtype=np.float32).astype(np.float64)
+    mean = x.sum(axis=0) / x.shape[0]
+    sd = np.sqrt(((x - mean) ** 2).sum(axis=0) / (x.shape[0] - 1))
+    return dict(mean=mean, sd=sd, min=x.min(axis=0), max=x.max(axis=0))

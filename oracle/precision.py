@@ -13,7 +13,7 @@ Paper passages:
 * Spreading: Appendix B eq. lambda_2_i in the precise-weight form
   w_i = max(w0_i, max_{j : r_ij < r_hi} w0_j * f_cut((r_ij - r_lo)/(r_hi - r_lo))).
   Time averages (eqs. lambda_3_i, lambda_4_i, csp_2_i) are not part of this evaluation.
-* Frozen atoms keep w = 0, get no CSP and are never sources (Appendix E subgroups).
+* Frozen atoms keep w = 0, get no CSP and are never sources (Appendix G, atom subgroups).
 
 Floating-point order (shared by definition with the library): every value below is
 computed with separately rounded operations in the order written.
@@ -115,17 +115,38 @@ def spread(pos, lo, hi, periodic, w0, r_lo, r_hi, frozen=None):
     return w
 
 
-def compute_precision(system, params, csr):
-    """Returns dict(csp, w0, w, mask, active) for ``system`` under ``params``."""
+def combine_extra(w, w0_extra, frozen=None):
+    """max(w, w0_extra) with frozen atoms kept at 0: an additional detection weight (the
+    learned criterion's) joined to a CSP-based weight."""
+    out = np.maximum(np.asarray(w, dtype=np.float64), np.asarray(w0_extra, dtype=np.float64))
+    if frozen is not None:
+        out = np.where(frozen.astype(bool), 0.0, out)
+    return out
+
+
+def compute_precision(system, params, csr, w0_extra=None, csp_given=None):
+    """Returns dict(csp, w0, w, mask, active) for ``system`` under ``params``.
+
+    ``w0_extra`` joins the CSP-based w0 before the spreading, or the spread weight after it
+    when ``params.extra_local`` is set (its detections are then not spread); ``csp_given``
+    replaces the CSP of the positions."""
     frozen = system.frozen
-    c = csp(system.pos, system.lo, system.hi, system.periodic, csr, r_cut=params.r_cut,
-            n_nn=params.n_nn, n_buffer=params.n_buffer, frozen=frozen)
+    if csp_given is None:
+        c = csp(system.pos, system.lo, system.hi, system.periodic, csr, r_cut=params.r_cut,
+                n_nn=params.n_nn, n_buffer=params.n_buffer, frozen=frozen)
+    else:
+        c = np.asarray(csp_given, dtype=np.float64)
     w0 = w0_from_csp(c, params.csp_lo, params.csp_hi, params.switch_kind, frozen)
+    local = getattr(params, "extra_local", False)
+    if w0_extra is not None and not local:
+        w0 = combine_extra(w0, w0_extra, frozen)
     w = spread(system.pos, system.lo, system.hi, system.periodic, w0, params.r_lo,
                params.r_hi, frozen)
+    if w0_extra is not None and local:
+        w = combine_extra(w, w0_extra, frozen)
     mask = (w > 0.0).astype(np.uint8)
     active = np.nonzero(mask)[0].astype(np.int64)
     return dict(csp=c, w0=w0, w=w, mask=mask, active=active)
 
 
-__all__ = ["f_cut", "csp", "w0_from_csp", "spread", "compute_precision", "min_image"]
+__all__ = ["f_cut", "csp", "w0_from_csp", "spread", "combine_extra", "compute_precision", "min_image"]

@@ -53,8 +53,7 @@ class AceEnergy(torch.autograd.Function):
         want = bool(ctx.needs_input_grad[1] or ctx.needs_input_grad[2])
         out = ops.ace_energy_forces(runner.ctx, atoms, nl, runner.model, active, runner.w, runner.precision,
                                     want_dc=want)
-        w = runner.w if runner.w is not None else torch.ones(n, dtype=torch.float64, device=p.device)
-        e = (w * out["e_site"]).sum()
+        e = ops.weighted_sum(runner.ctx, runner.w, out["e_site"])
         ctx.save_for_backward(out["f"], out.get("dE_dc1"), out.get("dE_dc2"))
         ctx.c_devices = (c1.device, c2.device)
         return e

@@ -18,6 +18,7 @@ APX_ENOMEM = -2
 APX_EDEVICE = -3
 APX_ECAPACITY = -4
 APX_ENONFINITE = -5
+APX_ERADICAND = -6
 APX_FP64 = 0
 APX_FP32 = 1
 MODE_ADAPTIVE = 0
@@ -57,23 +58,29 @@ class AceDesc(C.Structure):
                 ("anchored", C.c_int32), ("reserved", C.c_int32), ("anchor", EamParams)]
 
 
+class ThermoParams(C.Structure):
+    _fields_ = [("r_omega", C.c_double), ("omega_max", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
 class MdParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("mass", C.c_double), ("skin", C.c_double), ("max_nb", C.c_int32),
                 ("precision_every", C.c_int32), ("ace_precision", C.c_int32), ("mode", C.c_int32),
                 ("indenter", C.c_int32), ("avg_samples", C.c_int32), ("ind_radius", C.c_double),
                 ("ind_k", C.c_double), ("ind_center", C.c_double * 3), ("ind_velocity", C.c_double * 3),
-                ("avg_dw_min", C.c_double)]
+                ("avg_dw_min", C.c_double), ("avg_window", C.c_int32), ("thermostat", C.c_int32),
+                ("thermo", ThermoParams)]
 
 
 class AvgState(C.Structure):
-    _fields_ = [("n_avg", C.c_int32), ("reserved", C.c_int32), ("samples", C.c_int64), ("dw_min", C.c_double),
+    _fields_ = [("n_avg", C.c_int32), ("window", C.c_int32), ("samples", C.c_int64), ("dw_min", C.c_double),
                 ("csp_ring", _P), ("w_ring", _P)]
 
 
 class MdStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("precision_updates", C.c_int64),
                 ("n_active", C.c_int64), ("e_pot", C.c_double), ("e_kin", C.c_double),
-                ("e_indenter", C.c_double), ("ace_atoms", C.c_int64)]
+                ("e_indenter", C.c_double), ("ace_atoms", C.c_int64), ("thermo_steps", C.c_int64),
+                ("thermo_corrected", C.c_int64), ("thermo_failed", C.c_int64)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/apx.h
@@ -104,6 +111,10 @@ PROTOTYPES = {
                                           C.c_int32, _P, _P, _P, _P]),
     "apx_blend": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "apx_blend_noalloc": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "apx_thermostat_energy_errors": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                                                 C.c_double, _P]),
+    "apx_thermostat_correct": (C.c_int32, [_P, C.POINTER(Atoms), _P, _P, C.POINTER(ThermoParams), C.c_int64,
+                                           C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "apx_md_create": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(MdParams), C.POINTER(EamParams), _P,
                                   C.POINTER(PrecParams), C.POINTER(_P)]),
     "apx_md_destroy": (None, [_P]),
@@ -122,9 +133,15 @@ PROTOTYPES = {
     "apx_mlp_train_step": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int64, C.c_float, _P]),
     "apx_mlp_infer_bf16": (C.c_int32, [_P, _P, _P, C.c_int64, _P]),
     "apx_mlp_precision": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_double, C.c_double, _P, _P]),
+    "apx_mlp_weight": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_double, C.c_double, _P]),
+    "apx_mlp_labels": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P]),
+    "apx_mlp_feature_stats": (C.c_int32, [_P, _P, C.c_int64, _P]),
+    "apx_weighted_sum": (C.c_int32, [_P, C.c_int64, _P, _P, _P]),
 }
 MLP_PARAMS = 8705
 APX_PREC_CSP_GIVEN = 1
+APX_PREC_EXTRA_LOCAL = 2
+WINDOW_PAST, WINDOW_CURRENT = 0, 1
 
 _LIB = None
 

@@ -651,7 +651,8 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
                                                   int max_nb, const int* __restrict__ active, int n_act, int K,
                                                   T rc, T inv_h, double rc2, const T* __restrict__ Wp, AnchorDev an,
                                                   AceScratch<T> sc, const double* __restrict__ w,
-                                                  double* __restrict__ f) {
+                                                  double* __restrict__ f, const double* __restrict__ w2,
+                                                  double* __restrict__ f2) {
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
   constexpr int kMaxK = 12;
   extern __shared__ double smem_raw[];
@@ -660,6 +661,8 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   const int lane = threadIdx.x;
   const int i = active[q];
   const double wi = w ? w[i] : 1.0;
+  // second weight set (the integrator's weight difference): scattered only where non-zero
+  const double w2i = f2 ? w2[i] : 0.0;
   const int na = K * LM;
   const int ts = sc.tile_size;
   const T* Abr = ts > 0 ? sc.Ab + (size_t)(q / ts) * na * ts + (q % ts) : sc.Ab + (size_t)q * na;
@@ -692,6 +695,7 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   int cnt = count[i];
   if (cnt > max_nb) cnt = max_nb;
   double fix = 0.0, fiy = 0.0, fiz = 0.0;
+  double f2x = 0.0, f2y = 0.0, f2z = 0.0;
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const int k = c0 + lane;
     if (k < cnt) {
@@ -764,6 +768,17 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
         gy += s * dy;
         gz += s * dz;
       }
+      if (w2i != 0.0) {
+        const double hx = gx * w2i, hy = gy * w2i, hz = gz * w2i;
+        if (hx != 0.0 || hy != 0.0 || hz != 0.0) {
+          unsafeAtomicAdd(&f2[j], -hx);
+          unsafeAtomicAdd(&f2[(size_t)n + j], -hy);
+          unsafeAtomicAdd(&f2[2 * (size_t)n + j], -hz);
+        }
+        f2x += hx;
+        f2y += hy;
+        f2z += hz;
+      }
       gx *= wi;
       gy *= wi;
       gz *= wi;
@@ -784,6 +799,16 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
     unsafeAtomicAdd(&f[i], fix);
     unsafeAtomicAdd(&f[(size_t)n + i], fiy);
     unsafeAtomicAdd(&f[2 * (size_t)n + i], fiz);
+  }
+  if (w2i != 0.0) {  // uniform across the wave
+    f2x = wave_sum(f2x);
+    f2y = wave_sum(f2y);
+    f2z = wave_sum(f2z);
+    if (lane == 0) {
+      unsafeAtomicAdd(&f2[i], f2x);
+      unsafeAtomicAdd(&f2[(size_t)n + i], f2y);
+      unsafeAtomicAdd(&f2[2 * (size_t)n + i], f2z);
+    }
   }
 }
 
@@ -1192,7 +1217,8 @@ static apx_status ensure_lds(apx_ctx* ctx, const void* kern, size_t bytes) {
 template <class T, int LMAX>
 apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m,
                    const AceTables<T>& tb, const double* w, const int* active, int n_act, double* e_site,
-                   double* f, double* dc1, double* dc2, apx::DevBuf& buf) {
+                   double* f, double* dc1, double* dc2, apx::DevBuf& buf, const double* w2 = nullptr,
+                   double* f2 = nullptr) {
   constexpr int TILE = sizeof(T) == 4 ? 64 : 32;
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
   const int n = (int)atoms->n;
@@ -1344,7 +1370,8 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
   ProfScope ps(ctx, "ace.force");
   k_ace_force<T, LMAX><<<n_act, 64, lds3, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
-                                                         n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc, w, f);
+                                                         n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc, w, f, w2,
+                                                         f2);
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
 }
@@ -1357,10 +1384,10 @@ namespace {
 apx::DevBuf& ace_buffer(apx_ctx* ctx) { return ctx->ace_buf; }
 }  // namespace
 
-extern "C" apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
-                                            const apx_ace_model* m, const double* w, const int32_t* active,
-                                            int64_t n_active, int32_t precision, double* e_site, double* f,
-                                            double* dE_dc1, double* dE_dc2) {
+namespace {
+apx_status ace_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m, const double* w,
+                    const int32_t* active, int64_t n_active, int32_t precision, double* e_site, double* f,
+                    double* dE_dc1, double* dE_dc2, const double* w2, double* f2) {
   if (!ctx) return APX_EINVAL;
   apx_status s = check_atoms(ctx, atoms);
   if (s != APX_OK) return s;
@@ -1377,6 +1404,7 @@ extern "C" apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms
   if (n > 0) {
     k_fill_zero<<<blocks_for(3LL * n, 256), 256, 0, ctx->stream>>>(f, 3LL * n);
     k_fill_zero<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(e_site, n);
+    if (f2) k_fill_zero<<<blocks_for(3LL * n, 256), 256, 0, ctx->stream>>>(f2, 3LL * n);
     APX_LAUNCH_CHECK(ctx);
   }
   if (dE_dc1) {
@@ -1387,9 +1415,32 @@ extern "C" apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms
   if (n_active == 0) return APX_OK;
   const int na_ = (int)n_active;
   if (precision == APX_FP64) {
-    if (m->l_max == 3) return ace_run<double, 3>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
-    return ace_run<double, 4>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+    if (m->l_max == 3)
+      return ace_run<double, 3>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx),
+                                w2, f2);
+    return ace_run<double, 4>(ctx, atoms, nl, m, m->t64, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx),
+                              w2, f2);
   }
-  if (m->l_max == 3) return ace_run<float, 3>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
-  return ace_run<float, 4>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx));
+  if (m->l_max == 3)
+    return ace_run<float, 3>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx),
+                             w2, f2);
+  return ace_run<float, 4>(ctx, atoms, nl, m, m->t32, w, active, na_, e_site, f, dE_dc1, dE_dc2, ace_buffer(ctx),
+                           w2, f2);
+}
+}  // namespace
+
+namespace apx {
+apx_status ace_energy_forces_dual(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m,
+                                  const double* w, const double* w2, const int32_t* active, int64_t n_active,
+                                  int32_t precision, double* e_site, double* f, double* f2) {
+  if (!w2 || !f2) return fail(ctx, APX_EINVAL, "the second weight set and its force array are required");
+  return ace_impl(ctx, atoms, nl, m, w, active, n_active, precision, e_site, f, nullptr, nullptr, w2, f2);
+}
+}  // namespace apx
+
+extern "C" apx_status apx_ace_energy_forces(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
+                                            const apx_ace_model* m, const double* w, const int32_t* active,
+                                            int64_t n_active, int32_t precision, double* e_site, double* f,
+                                            double* dE_dc1, double* dE_dc2) {
+  return ace_impl(ctx, atoms, nl, m, w, active, n_active, precision, e_site, f, dE_dc1, dE_dc2, nullptr, nullptr);
 }

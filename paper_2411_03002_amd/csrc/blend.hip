@@ -45,6 +45,26 @@ __global__ void __launch_bounds__(kRedThreads) k_blend(long long n, const double
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+// Block partial sums of w_i e_i (w NULL: 1), reduced in the same fixed order as the blend.
+__global__ void __launch_bounds__(kRedThreads) k_wsum(long long n, const double* __restrict__ w,
+                                                      const double* __restrict__ e, double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  const long long base = (long long)blockIdx.x * kRedThreads * kRedPer;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kRedPer; ++k) {
+    const long long i = base + (long long)k * kRedThreads + threadIdx.x;
+    if (i < n) s += (w ? w[i] : 1.0) * e[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
 // Fixed-order pairwise sum of m partial values into *out (single block).
 __global__ void __launch_bounds__(kRedThreads) k_sum_partials(const double* __restrict__ partial, int m,
                                                               double* __restrict__ out) {
@@ -111,6 +131,22 @@ extern "C" apx_status apx_blend(apx_ctx* ctx, int64_t n, const double* w, const 
   } else {
     k_sum_partials<<<1, kRedThreads, 0, ctx->stream>>>(part, 0, e_pot);
   }
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}
+
+extern "C" apx_status apx_weighted_sum(apx_ctx* ctx, int64_t n, const double* w, const double* e, double* out) {
+  if (!ctx) return APX_EINVAL;
+  if (n < 0) return fail(ctx, APX_EINVAL, "negative size");
+  if ((n > 0 && !e) || !out) return fail(ctx, APX_EINVAL, "e and out are required");
+  const long long nb = n > 0 ? (n + kRedThreads * kRedPer - 1) / (kRedThreads * kRedPer) : 1;
+  APX_ALLOC(ctx, ctx->dtmp, sizeof(double) * (size_t)(nb + 1));
+  double* part = ctx->dtmp.as<double>();
+  if (n > 0) {
+    k_wsum<<<(unsigned)nb, kRedThreads, 0, ctx->stream>>>(n, w, e, part);
+    APX_LAUNCH_CHECK(ctx);
+  }
+  k_sum_partials<<<1, kRedThreads, 0, ctx->stream>>>(part, n > 0 ? (int)nb : 0, out);
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
 }

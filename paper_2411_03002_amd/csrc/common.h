@@ -112,6 +112,27 @@ apx_status scan_exclusive(apx_ctx* ctx, const int* in, long long m, int* out);
 // by apx_ctx_create with the context's device current.
 apx_status blend_scratch_setup(apx_ctx* ctx);
 
+// EAM energies and forces with weights w (as apx_eam_forces) plus, in the same density
+// pass, df[3][n] = F(weights wl) - F(weights w) of the fast part; scratch4 holds 4n doubles.
+apx_status eam_forces_dual(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_eam_params* p,
+                           const double* w, const double* wl, double* e_site, double* rho, double* f, double* df,
+                           double* scratch4);
+
+// ACE energies and forces as apx_ace_energy_forces with weights w, plus f2[3][n]
+// (overwritten) = -d/dx sum_i w2_i E_i over the same active atoms (w2 may be negative).
+apx_status ace_energy_forces_dual(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_ace_model* m,
+                                  const double* w, const double* w2, const int32_t* active, int64_t n_active,
+                                  int32_t precision, double* e_site, double* f, double* f2);
+
+// Local thermostat (thermostat.hip): energy errors and the group rescale, without the
+// argument checks of the entry points.
+apx_status thermostat_errors(apx_ctx* ctx, int64_t n, const uint8_t* frozen, const double* w_c, const double* w_d,
+                             const double* e_fast, const double* e_precise, const double* f_d, const double* df,
+                             const double* v_half, double dt, double mass, double* dE);
+apx_status thermostat_correct(apx_ctx* ctx, const apx_atoms* atoms, double* vel, const double* dE,
+                              const apx_thermo_params* p, int64_t step, double mass, int64_t* n_corrected,
+                              int64_t* n_failed);
+
 // Reads `count` ints from device memory into host memory (synchronising).
 apx_status read_ints(apx_ctx* ctx, const int* dev, int* host, int count);
 

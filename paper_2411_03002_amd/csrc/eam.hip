@@ -1,7 +1,7 @@
 // Embedded-atom model: density/embedding pass and site-weighted force pass.
 //
 // Sec. III B eq. energy_eam with the closed-form synthetic functions or the paper's EAM2
-// copper potential (Appendix D), chosen at compile time per launch; forces are the
+// copper potential (Appendix E), chosen at compile time per launch; forces are the
 // fast-potential part of Appendix C eq. F_i_d:
 //   F_i = -d/dx_i sum_k u_k E_k,  u = 1 - w
 //       = sum_j [ 1/2 (u_i + u_j) phi'(r_ij) + (u_i F'_i + u_j F'_j) rho'(r_ij) ] r_ij / r_ij
@@ -16,7 +16,7 @@ namespace apx {
 
 struct EamDev {
   double A, alpha, beta, r0, rc, inv_h, rc2;
-  // EAM2 (Appendix D), in the order of apx_eam_params.eam2
+  // EAM2 (Appendix E), in the order of apx_eam_params.eam2
   double E1, E2, delta, alpha1, alpha2, r01, r02, S[3], rs[3], a, beta1, beta2, r03, r04, xi0, xi2, q[4], Q1, Q2,
       f0;
 };
@@ -88,7 +88,9 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
                                                      const int* __restrict__ count, const int* __restrict__ idx,
                                                      int max_nb, const double* __restrict__ w,
                                                      double* __restrict__ e_site, double* __restrict__ rho_out,
-                                                     double* __restrict__ ufp, double* __restrict__ u_out) {
+                                                     double* __restrict__ ufp, double* __restrict__ u_out,
+                                                     const double* __restrict__ wl, double* __restrict__ dufp,
+                                                     double* __restrict__ du_out) {
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
@@ -142,9 +144,17 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
   const double u = w ? 1.0 - w[i] : 1.0;
   ufp[i] = u * Fp;
   u_out[i] = u;
+  if (dufp) {
+    // weights of a second set wl: the EAM weight difference (1 - wl) - (1 - w) = w - wl
+    const double du = w[i] - wl[i];
+    dufp[i] = du * Fp;
+    du_out[i] = du;
+  }
 }
 
-template <int KIND>
+// SKIPZERO: pairs whose two weights are both 0 contribute exactly 0 and are not evaluated
+// (the pass over weight differences, which are 0 almost everywhere).
+template <int KIND, bool SKIPZERO = false>
 __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ pos, int n, BoxDev b, EamDev p,
                                                    const int* __restrict__ count, const int* __restrict__ idx,
                                                    int max_nb, const double* __restrict__ ufp,
@@ -175,6 +185,7 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
       const double dy = min_image(py[q] - yi, b.L[1], b.half[1], b.per[1]);
       const double dz = min_image(pz[q] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
+      if (SKIPZERO && ui == 0.0 && uj[q] == 0.0) continue;
       if (k0 + q < cnt && r2 < p.rc2) {
         const double r = sqrt(r2);
         double ps, dps;
@@ -235,9 +246,13 @@ EamDev eam_dev(const apx_eam_params* p) {
   return d;
 }
 
-// Launches both passes; ufp/u are caller-provided scratch of n doubles each.
+// Launches both passes; ufp/u are caller-provided scratch of n doubles each.  With wl and
+// df (and dufp/du, n doubles each), a second force pass writes df = the fast-potential
+// force with weights wl minus the one with weights w.
 apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_eam_params* p,
-                      const double* w, double* e_site, double* rho, double* f, double* ufp, double* u) {
+                      const double* w, double* e_site, double* rho, double* f, double* ufp, double* u,
+                      const double* wl = nullptr, double* df = nullptr, double* dufp = nullptr,
+                      double* du = nullptr) {
   const int n = (int)atoms->n;
   if (n == 0) return APX_OK;
   BoxDev b = make_box(atoms);
@@ -246,11 +261,12 @@ apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
   ProfScope ps(ctx, "eam.density");
   if (p->kind == APX_EAM2)
     k_eam_density<APX_EAM2><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx,
-                                                                         nl->max_nb, w, e_site, rho, ufp, u);
+                                                                         nl->max_nb, w, e_site, rho, ufp, u, wl,
+                                                                         dufp, du);
   else
     k_eam_density<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
                                                                                nl->idx, nl->max_nb, w, e_site, rho,
-                                                                               ufp, u);
+                                                                               ufp, u, wl, dufp, du);
   APX_LAUNCH_CHECK(ctx);
   }
   ProfScope ps(ctx, "eam.force");
@@ -261,7 +277,28 @@ apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl,
     k_eam_force<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
                                                                              nl->idx, nl->max_nb, ufp, u, f);
   APX_LAUNCH_CHECK(ctx);
+  if (df) {
+    ProfScope pd(ctx, "eam.force_delta");
+    if (p->kind == APX_EAM2)
+      k_eam_force<APX_EAM2, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
+                                                                               nl->idx, nl->max_nb, dufp, du, df);
+    else
+      k_eam_force<APX_EAM_CLOSED, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+          atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb, dufp, du, df);
+    APX_LAUNCH_CHECK(ctx);
+  }
   return APX_OK;
+}
+
+apx_status eam_forces_dual(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_eam_params* p,
+                           const double* w, const double* wl, double* e_site, double* rho, double* f, double* df,
+                           double* scratch4) {
+  apx_status s = eam_check(ctx, atoms, nl, p);
+  if (s != APX_OK) return s;
+  if (!w || !wl || !df || !scratch4) return fail(ctx, APX_EINVAL, "dual EAM pass needs both weight sets");
+  const size_t n = (size_t)atoms->n;
+  return eam_launch(ctx, atoms, nl, p, w, e_site, rho, f, scratch4, scratch4 + n, wl, df, scratch4 + 2 * n,
+                    scratch4 + 3 * n);
 }
 
 }  // namespace apx

@@ -1,7 +1,10 @@
 // Velocity-Verlet integration with the switching-weight update (Sec. II C eq. vv) on one
 // GPU.  Per step: half kick + drift (+ wrap, displacement check), neighbour rebuild when
-// an atom moved more than skin/2 since the last build, the weight update every k steps,
-// EAM for every atom, ACE for the atoms with w > 0, blend, indenter, half kick.
+// an atom moved more than skin/2 since the last build, the weight update every k steps
+// (before the forces, or after them with time-averaged weights over past samples: the
+// force routine's order of Appendix G), EAM for every atom, ACE for the atoms with w > 0,
+// blend, indenter, half kick, and the local thermostat when the weights changed
+// (Sec. II C 2).
 #include <cmath>
 #include <cstring>
 
@@ -110,6 +113,28 @@ __global__ void k_copy_d(long long n, const double* __restrict__ a, double* __re
   if (i < n) b[i] = a[i];
 }
 
+// dw = w_c - w_d (the ACE weight of the force difference F^c - F^d) and the flag of the
+// atoms ACE is evaluated for when both weight sets are needed (w_c > 0 or w_d > 0).
+__global__ void k_union(int n, const double* __restrict__ wd, const double* __restrict__ wc, double* __restrict__ dw,
+                        int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = wd[i], c = wc[i];
+  dw[i] = c - a;
+  flag[i] = (a > 0.0 || c > 0.0) ? 1 : 0;
+}
+
+__global__ void k_compact_flags(int n, const int* __restrict__ flag, const int* __restrict__ pos_,
+                                int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) out[pos_[i]] = i;
+}
+
+__global__ void k_add_into(long long n, double* __restrict__ a, const double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] += b[i];
+}
+
 }  // namespace apx
 
 using namespace apx;
@@ -136,6 +161,13 @@ struct apx_md {
   DevBuf feat, pred, w0x;
   DevBuf csp_ring, w_ring, csp_avg, w_min;  // time-averaged weights (avg_samples > 0)
   long long avg_taken = 0;                  // samples in the rings since apx_md_init
+  DevBuf wtmp;                              // learned route: the centro-symmetry pass's weights
+  // local thermostat: weights of the last force evaluation, their difference, the force
+  // differences, energy errors, EAM scratch, the union of active atoms
+  DevBuf w_last, dw, df, df_ace, dE, eam4, uactive;
+  bool w_dirty = false;        // w differs from the weights of the last force evaluation
+  long long ace_count = 0;     // atoms ACE was evaluated for by the last force evaluation
+  long long thermo_corrected = 0, thermo_failed = 0;
   hipEvent_t ev[6] = {};
   double t_acc[5] = {0, 0, 0, 0, 0};
 };
@@ -184,6 +216,7 @@ apx_status md_precision(apx_md* md, const apx_nlist& nl, const apx_prec_params& 
                                  md->mask.as<uint8_t>(), md->active.as<int>(), na);
   apx_avg_state st{};
   st.n_avg = md->p.avg_samples;
+  st.window = md->p.avg_window;
   st.samples = md->avg_taken;
   st.dw_min = md->p.avg_dw_min;
   st.csp_ring = md->csp_ring.as<double>();
@@ -224,8 +257,10 @@ apx_status md_weights(apx_md* md, const double* pos, double* w) {
     apx_prec_params p0 = md->prec;
     p0.r_hi = 0.0;
     p0.flags = 0;
-    s = apx_compute_precision(ctx, &md->atoms, &nl, &p0, nullptr, md->csp.as<double>(), md->w0.as<double>(), w,
-                              md->mask.as<uint8_t>(), md->active.as<int>(), &na);
+    // the centro-symmetry pass writes its weights to scratch: w holds the previous filtered
+    // weights that the time-averaged pipeline reads
+    s = apx_compute_precision(ctx, &md->atoms, &nl, &p0, nullptr, md->csp.as<double>(), md->w0.as<double>(),
+                              md->wtmp.as<double>(), md->mask.as<uint8_t>(), md->active.as<int>(), &na);
     if (s != APX_OK) return s;
     s = apx_features(ctx, &md->atoms, &nl, md->rho.as<double>(), md->csp.as<double>(), md->f_eam.as<double>(),
                      md->feat.as<float>());
@@ -247,19 +282,28 @@ apx_status md_weights(apx_md* md, const double* pos, double* w) {
 }
 
 // Forces (and energies) at `pos` with weights `w`; f receives the total force including
-// the indenter at time t.  Events ev[1..4] bracket the kernel classes.
-apx_status md_forces(apx_md* md, const double* pos, const double* w, double* f, double t, bool timed) {
+// the indenter at time t.  Events ev[1..4] bracket the kernel classes.  dual: the weights
+// changed since the last force evaluation (md->w_last) and the thermostat is on: the
+// force difference F(w_last) - F(w) is formed in the same passes and the energy errors
+// are written to md->dE, with vel holding v(t + dt/2).
+apx_status md_forces(apx_md* md, const double* pos, const double* w, double* f, double t, bool timed,
+                     bool dual = false, const double* vel = nullptr) {
   apx_ctx* ctx = md->ctx;
   md->atoms.pos = pos;
   const long long n = md->n;
   apx_nlist nl;
   md_nlist(md, nl);
   double* scal = md->scal.as<double>();
+  const double* wl = md->w_last.as<double>();
   if (timed) APX_HIP(ctx, hipEventRecord(md->ev[2], ctx->stream));
   apx_status s;
   if (md->p.mode != APX_MODE_FULL_ACE) {
-    s = apx_eam_forces(ctx, &md->atoms, &nl, &md->eam, w, md->e_eam.as<double>(), md->rho.as<double>(),
-                       md->f_eam.as<double>());
+    if (dual)
+      s = eam_forces_dual(ctx, &md->atoms, &nl, &md->eam, w, wl, md->e_eam.as<double>(), md->rho.as<double>(),
+                          md->f_eam.as<double>(), md->df.as<double>(), md->eam4.as<double>());
+    else
+      s = apx_eam_forces(ctx, &md->atoms, &nl, &md->eam, w, md->e_eam.as<double>(), md->rho.as<double>(),
+                         md->f_eam.as<double>());
     if (s != APX_OK) return s;
   } else {
     k_fill_d<<<blocks_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, md->f_eam.as<double>(), 0.0);
@@ -268,18 +312,54 @@ apx_status md_forces(apx_md* md, const double* pos, const double* w, double* f, 
   }
   if (timed) APX_HIP(ctx, hipEventRecord(md->ev[3], ctx->stream));
   if (md->p.mode != APX_MODE_EAM && md->ace) {
-    s = apx_ace_energy_forces(ctx, &md->atoms, &nl, md->ace, w, md->active.as<int>(), md->n_active,
-                              md->p.ace_precision, md->e_ace.as<double>(), md->f_ace.as<double>(), nullptr, nullptr);
-    if (s != APX_OK) return s;
+    if (dual) {
+      // ACE over the atoms with either weight > 0; the second output is F(w_last) - F(w)
+      int* flag = md->uactive.as<int>() + n;
+      k_union<<<blocks_for(n, 256), 256, 0, ctx->stream>>>((int)n, w, wl, md->dw.as<double>(), flag);
+      APX_LAUNCH_CHECK(ctx);
+      APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
+      s = scan_exclusive(ctx, flag, n, ctx->itmp2.as<int>());
+      if (s != APX_OK) return s;
+      k_compact_flags<<<blocks_for(n, 256), 256, 0, ctx->stream>>>((int)n, flag, ctx->itmp2.as<int>(),
+                                                                   md->uactive.as<int>());
+      APX_LAUNCH_CHECK(ctx);
+      int nu = 0;
+      s = read_ints(ctx, ctx->itmp2.as<int>() + n, &nu, 1);
+      if (s != APX_OK) return s;
+      s = ace_energy_forces_dual(ctx, &md->atoms, &nl, md->ace, w, md->dw.as<double>(), md->uactive.as<int>(), nu,
+                                 md->p.ace_precision, md->e_ace.as<double>(), md->f_ace.as<double>(),
+                                 md->df_ace.as<double>());
+      if (s != APX_OK) return s;
+      md->ace_count = nu;
+    } else {
+      s = apx_ace_energy_forces(ctx, &md->atoms, &nl, md->ace, w, md->active.as<int>(), md->n_active,
+                                md->p.ace_precision, md->e_ace.as<double>(), md->f_ace.as<double>(), nullptr,
+                                nullptr);
+      if (s != APX_OK) return s;
+      md->ace_count = md->n_active;
+    }
   } else {
+    md->ace_count = 0;
     k_fill_d<<<blocks_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, md->f_ace.as<double>(), 0.0);
     k_fill_d<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, md->e_ace.as<double>(), 0.0);
+    if (dual) k_fill_d<<<blocks_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, md->df_ace.as<double>(), 0.0);
     APX_LAUNCH_CHECK(ctx);
   }
   if (timed) APX_HIP(ctx, hipEventRecord(md->ev[4], ctx->stream));
   s = apx_blend(ctx, n, w, md->e_eam.as<double>(), md->e_ace.as<double>(), md->f_eam.as<double>(),
                 md->f_ace.as<double>(), md->e_site.as<double>(), f, scal + 0);
   if (s != APX_OK) return s;
+  if (dual) {
+    // energy errors from the interatomic forces (f before the indenter is added)
+    if (md->p.mode == APX_MODE_FULL_ACE)
+      k_fill_d<<<blocks_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, md->df.as<double>(), 0.0);
+    k_add_into<<<blocks_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, md->df.as<double>(),
+                                                                md->df_ace.as<double>());
+    APX_LAUNCH_CHECK(ctx);
+    s = thermostat_errors(ctx, n, md->atoms.frozen, wl, w, md->e_eam.as<double>(), md->e_ace.as<double>(), f,
+                          md->df.as<double>(), vel, md->p.dt, md->p.mass, md->dE.as<double>());
+    if (s != APX_OK) return s;
+  }
   k_fill_d<<<1, 64, 0, ctx->stream>>>(1, scal + 2, 0.0);
   if (md->p.indenter) {
     const double cx = md->p.ind_center[0] + t * md->p.ind_velocity[0];
@@ -292,6 +372,10 @@ apx_status md_forces(apx_md* md, const double* pos, const double* w, double* f, 
   }
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
+}
+
+bool md_after_forces(const apx_md* md) {
+  return md->p.mode == APX_MODE_ADAPTIVE && md->p.avg_samples > 0 && md->p.avg_window == APX_WINDOW_PAST;
 }
 
 }  // namespace
@@ -313,6 +397,11 @@ extern "C" apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const 
   if (p->max_nb < 1 || p->max_nb > 128) return fail(ctx, APX_EINVAL, "max_nb must be in 1..128");
   if (p->avg_samples < 0 || p->avg_samples > 4096) return fail(ctx, APX_EINVAL, "avg_samples must be in 0..4096");
   if (p->avg_samples > 0 && !(p->avg_dw_min >= 0.0)) return fail(ctx, APX_EINVAL, "avg_dw_min must be >= 0");
+  if (p->avg_window != APX_WINDOW_PAST && p->avg_window != APX_WINDOW_CURRENT)
+    return fail(ctx, APX_EINVAL, "avg_window must be APX_WINDOW_PAST or APX_WINDOW_CURRENT");
+  if (p->thermostat != 0 && p->thermostat != 1) return fail(ctx, APX_EINVAL, "thermostat must be 0 or 1");
+  if (p->thermostat && (!(p->thermo.r_omega > 0.0) || p->thermo.omega_max < 1))
+    return fail(ctx, APX_EINVAL, "thermostat needs r_omega > 0 and omega_max >= 1");
   apx_md* md = new apx_md();
   md->ctx = ctx;
   md->p = *p;
@@ -344,6 +433,13 @@ extern "C" apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const 
     ok = md->csp_ring.ensure(ring) == hipSuccess && md->w_ring.ensure(ring) == hipSuccess &&
          md->csp_avg.ensure(sizeof(double) * n) == hipSuccess && md->w_min.ensure(sizeof(double) * n) == hipSuccess;
   }
+  if (ok && p->mode == APX_MODE_ADAPTIVE)
+    ok = md->wtmp.ensure(sizeof(double) * n) == hipSuccess;
+  if (ok && p->thermostat)
+    ok = md->w_last.ensure(sizeof(double) * n) == hipSuccess && md->dw.ensure(sizeof(double) * n) == hipSuccess &&
+         md->df.ensure(sizeof(double) * 3 * n) == hipSuccess &&
+         md->df_ace.ensure(sizeof(double) * 3 * n) == hipSuccess && md->dE.ensure(sizeof(double) * n) == hipSuccess &&
+         md->eam4.ensure(sizeof(double) * 4 * n) == hipSuccess && md->uactive.ensure(sizeof(int) * 2 * n) == hipSuccess;
   if (!ok) {
     delete md;
     return fail(ctx, APX_ENOMEM, "integrator buffers");
@@ -381,10 +477,36 @@ extern "C" apx_status apx_md_init(apx_md* md, const double* pos, double* f, doub
   if (s != APX_OK) return s;
   s = md_forces(md, pos, w, f, md->step * md->p.dt, false);
   if (s != APX_OK) return s;
+  if (md->p.thermostat) {
+    k_copy_d<<<blocks_for(md->n, 256), 256, 0, ctx->stream>>>(md->n, w, md->w_last.as<double>());
+    APX_LAUNCH_CHECK(ctx);
+  }
+  md->w_dirty = false;
   md->initialized = true;
   APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return APX_OK;
 }
+
+namespace {
+apx_status md_stats(apx_md* md, const double* vel, apx_md_stats st, apx_md_stats* out) {
+  apx_ctx* ctx = md->ctx;
+  const long long n = md->n;
+  double* scal = md->scal.as<double>();
+  k_fill_d<<<1, 64, 0, ctx->stream>>>(1, scal + 1, 0.0);
+  k_kinetic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, vel, md->atoms.frozen, 0.5 * md->p.mass / kAccel,
+                                                         scal + 1);
+  APX_LAUNCH_CHECK(ctx);
+  double h[3];
+  APX_HIP(ctx, hipMemcpyAsync(h, scal, sizeof(double) * 3, hipMemcpyDeviceToHost, ctx->stream));
+  APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  st.e_pot = h[0];
+  st.e_kin = h[1];
+  st.e_indenter = h[2];
+  st.n_active = md->n_active;
+  *out = st;
+  return APX_OK;
+}
+}  // namespace
 
 extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, double* f, double* w, int64_t n_steps,
                                       apx_md_stats* stats) {
@@ -422,18 +544,54 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     }
     APX_HIP(ctx, hipEventRecord(md->ev[1], ctx->stream));
     md->step += 1;
-    if (md->p.mode == APX_MODE_ADAPTIVE && md->p.precision_every > 0 && md->step % md->p.precision_every == 0) {
+    const bool due = md->p.mode == APX_MODE_ADAPTIVE && md->p.precision_every > 0 &&
+                     md->step % md->p.precision_every == 0;
+    const bool after = md_after_forces(md);
+    if (due && !after) {
       apx_status s = md_weights(md, pos, w);
       if (s != APX_OK) return s;
       ++st.precision_updates;
+      md->w_dirty = true;
     }
-    apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, true);
+    const bool dual = md->p.thermostat && md->w_dirty;
+    apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, true, dual, vel);
     if (s != APX_OK) return s;
-    st.ace_atoms += md->n_active;
+    st.ace_atoms += md->ace_count;
     {
     ProfScope ps(ctx, "md.kick");
     k_kick<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, vel, f, md->atoms.frozen, ck);
     APX_LAUNCH_CHECK(ctx);
+    }
+    bool radicand = false;
+    if (dual) {
+      int64_t nc = 0, nf = 0;
+      s = thermostat_correct(ctx, &md->atoms, vel, md->dE.as<double>(), &md->p.thermo, md->step, md->p.mass, &nc,
+                             &nf);
+      if (s != APX_OK) return s;
+      st.thermo_steps += 1;
+      st.thermo_corrected += nc;
+      st.thermo_failed += nf;
+      radicand = nf > 0;
+      k_copy_d<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, w, md->w_last.as<double>());
+      APX_LAUNCH_CHECK(ctx);
+    }
+    md->w_dirty = false;
+    if (due && after) {
+      s = md_weights(md, pos, w);
+      if (s != APX_OK) return s;
+      ++st.precision_updates;
+      md->w_dirty = true;
+    }
+    if (radicand) {
+      // a skipped correction: the step is complete; report it before taking the next one
+      APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
+      ++st.steps;
+      if (stats) {
+        s = md_stats(md, vel, st, stats);
+        if (s != APX_OK) return s;
+      }
+      return fail(ctx, APX_ERADICAND, "thermostat: %lld corrections at step %lld had a negative radicand",
+                  (long long)st.thermo_failed, md->step);
     }
     APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
     APX_HIP(ctx, hipEventSynchronize(md->ev[5]));
@@ -447,18 +605,8 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     ++st.steps;
   }
   if (stats) {
-    k_fill_d<<<1, 64, 0, ctx->stream>>>(1, scal + 1, 0.0);
-    k_kinetic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, vel, md->atoms.frozen, 0.5 * md->p.mass / kAccel,
-                                                           scal + 1);
-    APX_LAUNCH_CHECK(ctx);
-    double h[3];
-    APX_HIP(ctx, hipMemcpyAsync(h, scal, sizeof(double) * 3, hipMemcpyDeviceToHost, ctx->stream));
-    APX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    st.e_pot = h[0];
-    st.e_kin = h[1];
-    st.e_indenter = h[2];
-    st.n_active = md->n_active;
-    *stats = st;
+    apx_status s = md_stats(md, vel, st, stats);
+    if (s != APX_OK) return s;
   }
   return APX_OK;
 }

@@ -370,11 +370,98 @@ __global__ void k_mlp_w0(const float* __restrict__ pred, const float* __restrict
   w0[i] = w;
 }
 
+// Training labels: dF_i = |F^precise_i - F^fast_i| (float64), label_i = log(dF_i + 1e-3)
+// rounded to float32.
+__global__ void k_mlp_labels(long long n, const double* __restrict__ fp, const double* __restrict__ ff,
+                             double* __restrict__ dF, float* __restrict__ label) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dx = fp[i] - ff[i], dy = fp[n + i] - ff[n + i], dz = fp[2 * n + i] - ff[2 * n + i];
+  const double d = sqrt(dx * dx + dy * dy + dz * dz);
+  if (dF) dF[i] = d;
+  label[i] = (float)log(d + 1e-3);
+}
+
+// Column statistics of the [n][4] float32 features, one block per column, float64 sums
+// reduced in a fixed order: out[c] mean, out[4 + c] standard deviation with n - 1,
+// out[8 + c] minimum, out[12 + c] maximum.
+constexpr int kStatThreads = 1024;
+__global__ void __launch_bounds__(kStatThreads) k_feature_stats(const float* __restrict__ feat, long long n,
+                                                                double* __restrict__ out) {
+  __shared__ double sh[kStatThreads / kWave];
+  __shared__ double shm[kStatThreads / kWave], shx[kStatThreads / kWave];
+  const int c = blockIdx.x;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  double s = 0.0, mn = INFINITY, mx = -INFINITY;
+  for (long long i = threadIdx.x; i < n; i += kStatThreads) {
+    const double v = (double)feat[4 * i + c];
+    s += v;
+    mn = v < mn ? v : mn;
+    mx = v > mx ? v : mx;
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double a = __shfl_xor(mn, off, kWave), b = __shfl_xor(mx, off, kWave);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) {
+    sh[w] = s;
+    shm[w] = mn;
+    shx[w] = mx;
+  }
+  __syncthreads();
+  double tot = 0.0, tmin = INFINITY, tmax = -INFINITY;
+  for (int k = 0; k < kStatThreads / kWave; ++k) {
+    tot += sh[k];
+    tmin = shm[k] < tmin ? shm[k] : tmin;
+    tmax = shx[k] > tmax ? shx[k] : tmax;
+  }
+  const double mean = n > 0 ? tot / (double)n : 0.0;
+  __syncthreads();
+  double q = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kStatThreads) {
+    const double d = (double)feat[4 * i + c] - mean;
+    q += d * d;
+  }
+  q = wave_sum(q);
+  if (lane == 0) sh[w] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double qq = 0.0;
+    for (int k = 0; k < kStatThreads / kWave; ++k) qq += sh[k];
+    out[c] = mean;
+    out[4 + c] = n > 1 ? sqrt(qq / (double)(n - 1)) : 0.0;
+    out[8 + c] = tmin;
+    out[12 + c] = tmax;
+  }
+}
+
 }  // namespace apx
 
 using namespace apx;
 
 extern "C" {
+
+apx_status apx_mlp_labels(apx_ctx* ctx, int64_t n, const double* f_precise, const double* f_fast, double* dF,
+                          float* label) {
+  if (!ctx) return APX_EINVAL;
+  if (n < 0) return fail(ctx, APX_EINVAL, "negative size");
+  if (n > 0 && (!f_precise || !f_fast || !label)) return fail(ctx, APX_EINVAL, "forces and label are required");
+  if (n == 0) return APX_OK;
+  k_mlp_labels<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, f_precise, f_fast, dF, label);
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}
+
+apx_status apx_mlp_feature_stats(apx_ctx* ctx, const float* feat, int64_t n, double* stats) {
+  if (!ctx) return APX_EINVAL;
+  if (n < 1 || !feat || !stats) return fail(ctx, APX_EINVAL, "features (n >= 1) and stats are required");
+  k_feature_stats<<<4, kStatThreads, 0, ctx->stream>>>(feat, n, stats);
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}
 
 apx_status apx_mlp_create(apx_ctx* ctx, const float* params, const float* mu, const float* sd, apx_mlp** out) {
   if (!ctx) return APX_EINVAL;
@@ -518,13 +605,13 @@ apx_status apx_mlp_infer_bf16(apx_ctx* ctx, apx_mlp* m, const float* feat, int64
   return APX_OK;
 }
 
-apx_status apx_mlp_precision(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, double tau_lo, double tau_hi,
-                             float* pred, double* w0_extra) {
+apx_status apx_mlp_weight(apx_ctx* ctx, const apx_mlp* m, const float* pred, const float* feat, int64_t n,
+                          double tau_lo, double tau_hi, double* w0_extra) {
   if (!ctx || !m) return APX_EINVAL;
   if (!(tau_hi > tau_lo)) return fail(ctx, APX_EINVAL, "tau_hi must exceed tau_lo");
-  if (n > 0 && (!pred || !w0_extra)) return fail(ctx, APX_EINVAL, "pred and w0_extra are required");
-  apx_status s = apx_mlp_infer_bf16(ctx, m, feat, n, pred);
-  if (s != APX_OK || n == 0) return s;
+  if (n < 0 || n > 0x7fffffff) return fail(ctx, APX_EINVAL, "bad sample count");
+  if (n > 0 && (!pred || !feat || !w0_extra)) return fail(ctx, APX_EINVAL, "pred, feat and w0_extra are required");
+  if (n == 0) return APX_OK;
   Std4 lo, hi;
   for (int c = 0; c < 4; ++c) {
     lo.mu[c] = m->fmin[c];
@@ -534,6 +621,16 @@ apx_status apx_mlp_precision(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_
   k_mlp_w0<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pred, feat, (int)n, tau_lo, tau_hi - tau_lo, lo, hi, w0_extra);
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
+}
+
+apx_status apx_mlp_precision(apx_ctx* ctx, apx_mlp* m, const float* feat, int64_t n, double tau_lo, double tau_hi,
+                             float* pred, double* w0_extra) {
+  if (!ctx || !m) return APX_EINVAL;
+  if (!(tau_hi > tau_lo)) return fail(ctx, APX_EINVAL, "tau_hi must exceed tau_lo");
+  if (n > 0 && (!pred || !w0_extra)) return fail(ctx, APX_EINVAL, "pred and w0_extra are required");
+  apx_status s = apx_mlp_infer_bf16(ctx, m, feat, n, pred);
+  if (s != APX_OK || n == 0) return s;
+  return apx_mlp_weight(ctx, m, pred, feat, n, tau_lo, tau_hi, w0_extra);
 }
 
 }  // extern "C"

@@ -235,6 +235,16 @@ __global__ void __launch_bounds__(256) k_spread(const double* __restrict__ pos, 
   }
 }
 
+// The additional detection weight combined with the spread weight (no spreading of its
+// own): w = max(w, w0_extra), frozen atoms keep 0.
+__global__ void k_extra_local(int n, const uint8_t* __restrict__ frozen, const double* __restrict__ extra,
+                              double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (frozen && frozen[i])) return;
+  const double e = extra[i];
+  if (e > w[i]) w[i] = e;
+}
+
 __global__ void k_mask(int n, const double* __restrict__ w, uint8_t* __restrict__ mask, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -265,16 +275,31 @@ __device__ __forceinline__ double ring_mean(const double* __restrict__ ring, siz
   return acc / (double)m;
 }
 
-// eq. csp_2_i then eq. lambda_1_i: pushes the CSP sample, averages, switches; w0 seeds
-// the spreading target w.
+// eq. csp_2_i then eq. lambda_1_i: averages the CSP samples, pushes the new one, switches;
+// w0 seeds the spreading target w.  past: the mean holds the m samples before this call
+// (read before the new sample overwrites the oldest slot; the new sample alone when there
+// is none); current: the new sample and the m - 1 before it.
 __global__ void k_avg_csp(int n, const uint8_t* __restrict__ frozen, PrecDev p, const double* __restrict__ w0_extra,
                           const double* __restrict__ csp, double* __restrict__ ring, int slot, int n_avg, int m,
-                          double* __restrict__ csp_avg, double* __restrict__ w0, double* __restrict__ w) {
+                          int past, double* __restrict__ csp_avg, double* __restrict__ w0, double* __restrict__ w) {
+#pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double c = csp[i];
-  ring[(size_t)slot * n + i] = c;
-  const double a = ring_mean(ring, (size_t)n, i, slot, n_avg, m, c);
+  double a;
+  if (past && m > 0) {
+    double acc = 0.0;
+    int s = slot;
+    for (int j = 0; j < m; ++j) {
+      s = s == 0 ? n_avg - 1 : s - 1;
+      acc = acc + ring[(size_t)s * n + i];
+    }
+    a = acc / (double)m;
+    ring[(size_t)slot * n + i] = c;
+  } else {
+    ring[(size_t)slot * n + i] = c;
+    a = ring_mean(ring, (size_t)n, i, slot, n_avg, past ? 1 : m, c);
+  }
   csp_avg[i] = a;
   if (frozen && frozen[i]) {
     w0[i] = 0.0;
@@ -340,6 +365,7 @@ namespace {
 // the buffers (all device, length n or [n_avg][n]).
 struct AvgArgs {
   int n_avg, slot, m, first;
+  int past, m_csp;  // window of the CSP mean: past samples only (m_csp of them) or current
   double dw_min;
   double *csp_ring, *w_ring, *csp_avg, *w_min, *w_avg;
 };
@@ -372,24 +398,28 @@ apx_status precision_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist*
   pd.rc2 = p->r_cut * p->r_cut;
   // spreading target: w itself, or the instantaneous weight when averaging
   double* ws = avg ? avg->w_min : w;
+  // the extra detection weight enters before spreading, or after it (APX_PREC_EXTRA_LOCAL)
+  const bool extra_local = (p->flags & APX_PREC_EXTRA_LOCAL) != 0;
+  const double* extra_pre = extra_local ? nullptr : w0_extra;
   if (!(p->flags & APX_PREC_CSP_GIVEN)) {
   ProfScope ps(ctx, "prec.csp");
   if (pd.m == 12 && pd.half == 6)
     k_csp<12, 6, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, ws);
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, avg ? nullptr : extra_pre, csp, w0, ws);
   else
     k_csp<kMaxM, kMaxHalf, false><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, w0_extra, csp, w0, ws);
+        atoms->pos, n, g, atoms->frozen, nl->count, nl->idx, nl->max_nb, pd, avg ? nullptr : extra_pre, csp, w0, ws);
   APX_LAUNCH_CHECK(ctx);
   } else if (!avg) {
     ProfScope ps(ctx, "prec.switch");
-    k_switch<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, w0, w);
+    k_switch<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, extra_pre, csp, w0, w);
     APX_LAUNCH_CHECK(ctx);
   }
   if (avg) {
     ProfScope ps(ctx, "prec.avg_csp");
-    k_avg_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, w0_extra, csp, avg->csp_ring,
-                                                           avg->slot, avg->n_avg, avg->m, avg->csp_avg, w0, ws);
+    k_avg_csp<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, pd, extra_pre, csp, avg->csp_ring,
+                                                           avg->slot, avg->n_avg, avg->past ? avg->m_csp : avg->m,
+                                                           avg->past, avg->csp_avg, w0, ws);
     APX_LAUNCH_CHECK(ctx);
   }
   if (p->r_hi > 0.0) {
@@ -418,6 +448,10 @@ apx_status precision_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist*
           ctx->cell_atoms.as<int>(), reinterpret_cast<unsigned long long*>(ws));
       APX_LAUNCH_CHECK(ctx);
     }
+  }
+  if (extra_local && w0_extra) {
+    k_extra_local<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, atoms->frozen, w0_extra, ws);
+    APX_LAUNCH_CHECK(ctx);
   }
   APX_ALLOC(ctx, ctx->itmp, sizeof(int) * (size_t)n);
   APX_ALLOC(ctx, ctx->itmp2, sizeof(int) * (size_t)(n + 1));
@@ -462,6 +496,8 @@ extern "C" apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* a
   if (!st || !atoms) return fail(ctx, APX_EINVAL, "atoms and the averaging state are required");
   if (st->n_avg < 1 || st->n_avg > kMaxAvg) return fail(ctx, APX_EINVAL, "n_avg must be in 1..%d", kMaxAvg);
   if (st->samples < 0) return fail(ctx, APX_EINVAL, "samples must be >= 0");
+  if (st->window != APX_WINDOW_PAST && st->window != APX_WINDOW_CURRENT)
+    return fail(ctx, APX_EINVAL, "window must be APX_WINDOW_PAST or APX_WINDOW_CURRENT");
   if (!(st->dw_min >= 0.0)) return fail(ctx, APX_EINVAL, "dw_min must be >= 0");
   if (atoms->n > 0 && (!st->csp_ring || !st->w_ring || !csp_avg || !w_min))
     return fail(ctx, APX_EINVAL, "rings, csp_avg and w_min are required");
@@ -470,6 +506,8 @@ extern "C" apx_status apx_compute_precision_avg(apx_ctx* ctx, const apx_atoms* a
   a.slot = (int)(st->samples % st->n_avg);
   a.m = st->samples + 1 < st->n_avg ? (int)st->samples + 1 : st->n_avg;
   a.first = st->samples == 0 ? 1 : 0;
+  a.past = st->window == APX_WINDOW_PAST ? 1 : 0;
+  a.m_csp = st->samples < st->n_avg ? (int)st->samples : st->n_avg;  // samples before this one
   a.dw_min = st->dw_min;
   a.csp_ring = st->csp_ring;
   a.w_ring = st->w_ring;

@@ -9,7 +9,9 @@ detection weight combined with the centro-symmetry weight by max (the centro-sym
 criterion stays as fallback: atoms with features outside the training range use it
 alone), followed by the usual spreading.
 
-Everything that computes runs in libapx.so; this module only orders the calls.
+Every step of the method (labels, input statistics, training, inference, weights) runs in
+libapx.so; this module orders the calls.  `assess` is the evaluation of a result, not part
+of the method.
 """
 
 from __future__ import annotations
@@ -68,8 +70,7 @@ def snapshot(ctx: ops.Context, system, eam, ace: ops.AceModel, prec, precision: 
     feat = ops.features(ctx, atoms, nl, e["rho"], pr["csp"], e["f"])
     everyone = torch.arange(atoms.n, dtype=torch.int32, device=atoms.pos.device)
     a = ops.ace_energy_forces(ctx, atoms, nl, ace, everyone, None, precision)
-    dF = (a["f"] - e["f"]).norm(dim=0)
-    label = torch.log(dF + EPS_LABEL).to(torch.float32)
+    dF, label = ops.mlp_labels(ctx, a["f"], e["f"])
     return Snapshot(feat, label, dF, pr["csp"])
 
 
@@ -77,10 +78,10 @@ def train(ctx: ops.Context, feat: torch.Tensor, label: torch.Tensor, *, epochs: 
           lr: float = 1e-3, seed: int = 0, log=None) -> ops.Mlp:
     """Adam on the mean squared error with shuffled mini-batches; returns the network with
     its input standardisation and feature range set from the training data."""
-    mu = feat.mean(dim=0).cpu().numpy()
-    sd = feat.std(dim=0).clamp_min(1e-6).cpu().numpy()
-    net = ops.Mlp(ctx, glorot_params(seed), mu, sd)
-    net.set_range(feat.min(dim=0).values.cpu().numpy(), feat.max(dim=0).values.cpu().numpy())
+    st = ops.feature_stats(ctx, feat)
+    sd = np.maximum(st["sd"], 1e-6)
+    net = ops.Mlp(ctx, glorot_params(seed), st["mean"], sd)
+    net.set_range(st["min"], st["max"])
     n = feat.shape[0]
     g = torch.Generator().manual_seed(seed)
     for ep in range(epochs):

@@ -149,7 +149,8 @@ def build_neighbors(ctx: Context, atoms: DeviceAtoms, r_list: float, max_nb: int
 
 def prec_struct(p, csp_given: bool = False) -> B.PrecParams:
     s = B.PrecParams()
-    s.flags = B.APX_PREC_CSP_GIVEN if csp_given else 0
+    s.flags = (B.APX_PREC_CSP_GIVEN if csp_given else 0) | \
+        (B.APX_PREC_EXTRA_LOCAL if getattr(p, "extra_local", False) else 0)
     s.n_nn = int(getattr(p, "n_nn", 12))
     s.n_buffer = int(getattr(p, "n_buffer", 0))
     s.switch_kind = int(p.switch_kind)
@@ -204,8 +205,9 @@ class TimeAveragedSwitch:
     """State of apx_compute_precision_avg: the CSP and spread-weight rings [n_avg][n], the
     sample counter and the filtered weight w (kept between calls)."""
 
-    def __init__(self, n: int, n_avg: int, dw_min: float, device="cuda"):
+    def __init__(self, n: int, n_avg: int, dw_min: float, device="cuda", window: str = "past"):
         self.n, self.n_avg, self.dw_min = int(n), int(n_avg), float(dw_min)
+        self.window = {"past": B.WINDOW_PAST, "current": B.WINDOW_CURRENT}[window]
         self.csp_ring = torch.zeros((self.n_avg, self.n), dtype=torch.float64, device=device)
         self.w_ring = torch.zeros((self.n_avg, self.n), dtype=torch.float64, device=device)
         self.w = torch.zeros(self.n, dtype=torch.float64, device=device)
@@ -224,7 +226,8 @@ class TimeAveragedSwitch:
                    w0=torch.empty(n, **f64), w_min=torch.empty(n, **f64), w_avg=torch.empty(n, **f64),
                    mask=torch.empty(n, dtype=torch.uint8, device=dev),
                    active=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
-        st = B.AvgState(self.n_avg, 0, self.samples, self.dw_min, self.csp_ring.data_ptr(), self.w_ring.data_ptr())
+        st = B.AvgState(self.n_avg, self.window, self.samples, self.dw_min, self.csp_ring.data_ptr(),
+                        self.w_ring.data_ptr())
         na = C.c_int64(0)
         a, s, pp = atoms.struct(), nl.struct(), prec_struct(params, csp is not None)
         ctx._check(ctx.lib.apx_compute_precision_avg(ctx.h, C.byref(a), C.byref(s), C.byref(pp), C.byref(st),
@@ -353,11 +356,17 @@ class MD:
 
     def __init__(self, ctx: Context, atoms: DeviceAtoms, eam, ace: AceModel | None, prec, *, dt=1e-3,
                  mass=63.546, skin=0.5, max_nb=80, precision_every=10, ace_precision="fp32",
-                 mode="adaptive", indenter=None, avg_samples=0, avg_dw_min=0.0):
+                 mode="adaptive", indenter=None, avg_samples=0, avg_dw_min=0.0, avg_window="past",
+                 thermostat=None):
+        """``thermostat``: None, or dict(r_omega, omega_max, seed) for the local thermostat."""
         self.ctx = ctx
         self.atoms = atoms
         p = B.MdParams()
         p.avg_samples, p.avg_dw_min = int(avg_samples), float(avg_dw_min)
+        p.avg_window = {"past": B.WINDOW_PAST, "current": B.WINDOW_CURRENT}[avg_window]
+        if thermostat is not None:
+            p.thermostat = 1
+            p.thermo = thermo_struct(thermostat)
         p.dt, p.mass, p.skin, p.max_nb = float(dt), float(mass), float(skin), int(max_nb)
         p.precision_every = int(precision_every)
         p.ace_precision = B.APX_FP32 if ace_precision == "fp32" else B.APX_FP64
@@ -389,12 +398,17 @@ class MD:
         self.ctx._check(self.ctx.lib.apx_md_init(self.h, _p(pos), _p(f), _p(w)))
         return f, w
 
-    def step(self, pos, vel, f, w, n_steps: int) -> dict:
+    def step(self, pos, vel, f, w, n_steps: int, allow_radicand: bool = False) -> dict:
+        """apx_verlet_step; with ``allow_radicand`` a skipped thermostat correction returns
+        the stats (key ``status``) instead of raising."""
         self.ctx.bind_stream()
         st = B.MdStats()
-        self.ctx._check(self.ctx.lib.apx_verlet_step(self.h, _p(pos), _p(vel), _p(f), _p(w), int(n_steps),
-                                                     C.byref(st)))
-        return {k: getattr(st, k) for k, _ in B.MdStats._fields_}
+        code = self.ctx.lib.apx_verlet_step(self.h, _p(pos), _p(vel), _p(f), _p(w), int(n_steps), C.byref(st))
+        if not (allow_radicand and code == B.APX_ERADICAND):
+            self.ctx._check(code)
+        out = {k: getattr(st, k) for k, _ in B.MdStats._fields_}
+        out["status"] = int(code)
+        return out
 
     def set_mlp(self, net, tau_lo: float, tau_hi: float):
         """Learned criterion (None: centro-symmetry alone)."""
@@ -417,6 +431,67 @@ class MD:
             self.close()
         except Exception:
             pass
+
+
+def mlp_labels(ctx: Context, f_precise, f_fast):
+    """apx_mlp_labels: (dF float64 [n], label float32 [n])."""
+    ctx.bind_stream()
+    n = int(f_precise.shape[1])
+    dF = torch.empty(n, dtype=torch.float64, device=f_precise.device)
+    label = torch.empty(n, dtype=torch.float32, device=f_precise.device)
+    ctx._check(ctx.lib.apx_mlp_labels(ctx.h, n, _p(f_precise), _p(f_fast), _p(dF), _p(label)))
+    return dF, label
+
+
+def feature_stats(ctx: Context, feat) -> dict:
+    """apx_mlp_feature_stats: per-column mean, sd (n - 1), min and max (host float64 [4] each)."""
+    ctx.bind_stream()
+    out = torch.empty(16, dtype=torch.float64, device=feat.device)
+    ctx._check(ctx.lib.apx_mlp_feature_stats(ctx.h, _p(feat), int(feat.shape[0]), _p(out)))
+    v = out.cpu().numpy()
+    return dict(mean=v[0:4], sd=v[4:8], min=v[8:12], max=v[12:16])
+
+
+def weighted_sum(ctx: Context, w, e) -> torch.Tensor:
+    """apx_weighted_sum: 0-d tensor sum_i w_i e_i (w None: all 1)."""
+    ctx.bind_stream()
+    out = torch.empty((), dtype=torch.float64, device=e.device)
+    ctx._check(ctx.lib.apx_weighted_sum(ctx.h, int(e.numel()), _p(w), _p(e), _p(out)))
+    return out
+
+
+def thermo_struct(p) -> B.ThermoParams:
+    t = B.ThermoParams()
+    t.r_omega = float(p["r_omega"])
+    t.omega_max = int(p["omega_max"])
+    t.seed = int(p["seed"])
+    return t
+
+
+def thermostat_energy_errors(ctx: Context, w_c, w_d, e_fast, e_precise, f_d, df, v_half, dt: float, mass: float,
+                             frozen=None) -> torch.Tensor:
+    """apx_thermostat_energy_errors: dE [n]."""
+    ctx.bind_stream()
+    n = int(w_c.numel())
+    dE = torch.empty(n, dtype=torch.float64, device=w_c.device)
+    ctx._check(ctx.lib.apx_thermostat_energy_errors(ctx.h, n, _p(frozen), _p(w_c), _p(w_d), _p(e_fast),
+                                                    _p(e_precise), _p(f_d), _p(df), _p(v_half), float(dt),
+                                                    float(mass), _p(dE)))
+    return dE
+
+
+def thermostat_correct(ctx: Context, atoms: DeviceAtoms, vel, dE, params, step: int, mass: float,
+                       allow_radicand: bool = False) -> dict:
+    """apx_thermostat_correct on ``vel`` (in place): dict(corrected, failed, status)."""
+    ctx.bind_stream()
+    a = atoms.struct()
+    tp = thermo_struct(params)
+    nc, nf = C.c_int64(0), C.c_int64(0)
+    code = ctx.lib.apx_thermostat_correct(ctx.h, C.byref(a), _p(vel), _p(dE), C.byref(tp), int(step), float(mass),
+                                          C.byref(nc), C.byref(nf))
+    if not (allow_radicand and code == B.APX_ERADICAND):
+        ctx._check(code)
+    return dict(corrected=int(nc.value), failed=int(nf.value), status=int(code))
 
 
 def features(ctx: Context, atoms: DeviceAtoms, nl: NeighborList, rho, csp, f_eam) -> torch.Tensor:
@@ -485,6 +560,15 @@ class Mlp:
         out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
         self.ctx._check(self.ctx.lib.apx_mlp_infer_bf16(self.ctx.h, self.h, _p(feat), feat.shape[0], _p(out)))
         return out
+
+    def weight(self, pred: torch.Tensor, feat: torch.Tensor, tau_lo: float, tau_hi: float) -> torch.Tensor:
+        """apx_mlp_weight: the learned detection weight of given predictions."""
+        self.ctx.bind_stream()
+        n = int(pred.numel())
+        w0 = torch.empty(n, dtype=torch.float64, device=pred.device)
+        self.ctx._check(self.ctx.lib.apx_mlp_weight(self.ctx.h, self.h, _p(pred), _p(feat), n, float(tau_lo),
+                                                    float(tau_hi), _p(w0)))
+        return w0
 
     def precision(self, feat: torch.Tensor, tau_lo: float, tau_hi: float):
         self.ctx.bind_stream()

@@ -30,7 +30,7 @@ class EamParams:
 
 @dataclasses.dataclass(frozen=True)
 class Eam2Params:
-    """The paper's EAM2 copper potential (Appendix D): pair potential Phi of two Morse-like
+    """The paper's EAM2 copper potential (Appendix E): pair potential Phi of two Morse-like
     terms, a constant delta and three short-range repulsions S_n; density zeta of a
     Gaussian and an exponential term; embedding xi piecewise around xi(1) = xi0, shifted
     by f0 (the fit's energy offset, Sec. III B); taper psi((r - rc)/h)."""
@@ -60,7 +60,7 @@ class Eam2Params:
 
 
 def eam2_original() -> Eam2Params:
-    """Appendix D, Table II, column 'Value original' (EAM2 of Mishin et al.)."""
+    """Appendix E, Table III, column 'Value original' (EAM2 of Mishin et al.)."""
     return Eam2Params(E1=2.01458e+02, E2=6.59288e-03, delta=8.62250e-03, alpha1=2.97758e+00, alpha2=1.54927e+00,
                       r01=8.35910e-01, r02=4.46867e+00, S=(4.0, 40.0, 1150.0), rs=(2.24, 1.80, 1.20),
                       a=3.80362e+00, beta1=1.73940e-01, beta2=5.35661e+02, r03=-2.19885e+00, r04=-2.61984e+02,
@@ -69,7 +69,7 @@ def eam2_original() -> Eam2Params:
 
 
 def eam2_fit300k() -> Eam2Params:
-    """Appendix D, Table II, column 'Value fit 300K' (the paper's refit, F_0^Fit included)."""
+    """Appendix E, Table III, column 'Value fit 300K' (the paper's refit, F_0^Fit included)."""
     return Eam2Params(E1=2.01486e+02, E2=6.44057e-03, delta=2.18016e-02, alpha1=2.96972e+00, alpha2=1.55510e+00,
                       r01=8.36347e-01, r02=4.46690e+00, S=(4.0, 40.0, 1150.0), rs=(2.24, 1.80, 1.20),
                       a=3.80541e+00, beta1=1.66589e-01, beta2=5.35661e+02, r03=-2.19834e+00, r04=-2.61984e+02,
@@ -101,7 +101,8 @@ class PrecisionParams:
 
     ``switch_kind`` 0: w0 = clamp((CSP-lo)/(hi-lo), 0, 1); 1: w0 = 1 - f_cut((CSP-lo)/(hi-lo)).
     ``r_hi`` = 0 disables spreading.  ``n_nn`` nearest neighbours (``+ n_buffer``) enter
-    the centro-symmetry parameter; neighbours are taken within ``r_cut``.
+    the centro-symmetry parameter; neighbours are taken within ``r_cut``.  ``extra_local``:
+    an additional detection weight (the learned criterion's) joins after the spreading.
     """
 
     csp_lo: float
@@ -112,6 +113,7 @@ class PrecisionParams:
     n_nn: int = 12
     n_buffer: int = 0
     r_cut: float = 5.0
+    extra_local: bool = False
 
 
 def eam_cu_like(a: float = A_CU) -> EamParams:
@@ -168,7 +170,7 @@ def precision_hyb1() -> PrecisionParams:
 
 
 def precision_hyb2() -> PrecisionParams:
-    """The paper's Hyb2 set (Appendix H): Hyb1 with spreading radii 8/20 A."""
+    """The paper's Hyb2 set (Appendix K): Hyb1 with spreading radii 8/20 A."""
     return PrecisionParams(csp_lo=2.5, csp_hi=3.0, switch_kind=1, r_lo=8.0, r_hi=20.0)
 
 

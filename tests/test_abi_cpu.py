@@ -44,7 +44,7 @@ def test_struct_layouts_match_c(tmp_path):
     structs = {"apx_atoms": binding.Atoms, "apx_nlist": binding.NList, "apx_prec_params": binding.PrecParams,
                "apx_eam_params": binding.EamParams, "apx_ace_desc": binding.AceDesc,
                "apx_md_params": binding.MdParams, "apx_md_stats": binding.MdStats,
-               "apx_avg_state": binding.AvgState}
+               "apx_avg_state": binding.AvgState, "apx_thermo_params": binding.ThermoParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "apx.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

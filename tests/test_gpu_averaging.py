@@ -3,8 +3,10 @@
 A sequence of calls on perturbed positions (more calls than ring slots, so the rings
 wrap; a minimum step that holds some weights) compares every output of every call:
 the instantaneous and averaged CSP, w0, the spread weight, its mean, the filtered
-weight, the mask and the active list.  The integrator's averaged weights are compared
-with the oracle at every weight update of a short run.
+weight, the mask and the active list, under both readings of the CSP window (the past
+samples of eq. csp_2_i, and the current window).  The integrator with averaged weights
+is compared with the oracle's own trajectory from the same start (the sample of an update
+step taken after its forces with the past window, before them with the current one).
 """
 
 import numpy as np
@@ -14,7 +16,7 @@ import torch
 import synth
 from synth import configs
 from oracle import ace as oace
-from oracle import averaging, geometry
+from oracle import averaging, geometry, precision, verlet
 
 pytestmark = pytest.mark.gpu
 
@@ -65,16 +67,17 @@ def _compare(out, ref):
     assert np.array_equal(out["active"].cpu().numpy(), ref["active"])
 
 
+@pytest.mark.parametrize("window", ["past", "current"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_time_averaged_switching_parity(ops_ctx, case):
+def test_time_averaged_switching_parity(ops_ctx, case, window):
     ops, ctx = ops_ctx
     make, n_avg, dw, calls, noise = CASES[case]
-    _case(f"time-averaged switching {case}")
+    _case(f"time-averaged switching {case}, {window} window")
     s = make()
     p = synth.precision_static()
     rng = np.random.default_rng(77)
-    ora = averaging.TimeAveragedSwitch(n_avg, dw)
-    dev = ops.TimeAveragedSwitch(s.n, n_avg, dw)
+    ora = averaging.TimeAveragedSwitch(n_avg, dw, window=window)
+    dev = ops.TimeAveragedSwitch(s.n, n_avg, dw, window=window)
     held = 0
     base = s.pos.copy()
     for k in range(calls):
@@ -93,11 +96,16 @@ def test_time_averaged_switching_parity(ops_ctx, case):
         assert held > 0
 
 
-def test_given_csp_and_extra_weight(ops_ctx):
+@pytest.mark.parametrize("extra_local", [False, True])
+def test_given_csp_and_extra_weight(ops_ctx, extra_local):
+    """A given CSP (with +inf entries) and an extra detection weight joined before the
+    spreading or, with extra_local, after it: the averaged pipeline and the instantaneous
+    evaluation, bit for bit."""
+    import dataclasses
     ops, ctx = ops_ctx
-    _case("time-averaged switching, given CSP and extra detection weight")
+    _case(f"time-averaged switching, given CSP and extra detection weight, extra_local={extra_local}")
     s = _slab()
-    p = synth.precision_static()
+    p = dataclasses.replace(synth.precision_static(), extra_local=extra_local)
     rng = np.random.default_rng(5)
     ora = averaging.TimeAveragedSwitch(3, 0.05)
     dev = ops.TimeAveragedSwitch(s.n, 3, 0.05)
@@ -108,10 +116,16 @@ def test_given_csp_and_extra_weight(ops_ctx):
         c = rng.uniform(0.0, 4.0, size=s.n)
         c[rng.choice(s.n, 3, replace=False)] = np.inf
         extra = np.where(rng.uniform(size=s.n) < 0.05, rng.uniform(0.0, 1.0, size=s.n), 0.0)
-        out = dev.update(ctx, atoms, nl, p, w0_extra=torch.as_tensor(extra, device="cuda"),
-                         csp=torch.as_tensor(c, device="cuda"))
+        ex_d = torch.as_tensor(extra, device="cuda")
+        c_d = torch.as_tensor(c, device="cuda")
+        out = dev.update(ctx, atoms, nl, p, w0_extra=ex_d, csp=c_d)
         ref = ora.update(s, p, csr, w0_extra=extra, csp=c)
         _compare(out, ref)
+        inst = ops.compute_precision(ctx, atoms, nl, p, w0_extra=ex_d, csp=c_d.clone())
+        iref = precision.compute_precision(s, p, csr, w0_extra=extra, csp_given=c)
+        for key in ("w0", "w", "mask"):
+            assert np.array_equal(inst[key].cpu().numpy(), iref[key]), key
+        assert np.array_equal(inst["active"].cpu().numpy(), iref["active"])
 
 
 def test_argument_errors(ops_ctx):
@@ -136,34 +150,34 @@ def test_argument_errors(ops_ctx):
         dev.update(ctx, atoms, nl, p)
 
 
-def test_integrator_time_averaged_weights(ops_ctx):
-    """The integrator samples at apx_md_init and after the drift of every second step; its
-    weights after each update equal the oracle's pipeline on the same positions."""
+@pytest.mark.parametrize("window", ["past", "current"])
+def test_integrator_time_averaged_weights(ops_ctx, window):
+    """The integrator with averaged weights (N = 3, minimum step 0.05, a sample every
+    second step) against the oracle integrator from the same start: positions, velocities
+    and weights after 12 steps, float64 ACE."""
     ops, ctx = ops_ctx
-    _case("integrator with time-averaged weights, slab, 12 steps")
+    _case(f"integrator with time-averaged weights, slab, 12 steps, {window} window")
     s = configs.slab100(4, 4, 6, seed=33, temperature=600.0, sigma=0.1)
     p = synth.precision_static()
     prm = synth.ace_random(8, 3, oace.num_basis(8, 3), seed=5, anchored=True)
+    eam_p = synth.eam_cu_like()
+    ref = verlet.run(s, eam_p, prm, p, 1e-3, 12, precision_every=2,
+                     avg=dict(n_avg=3, dw_min=0.05, window=window))
     atoms = ops.device_atoms(s)
     model = ops.AceModel(ctx, prm)
-    md = ops.MD(ctx, atoms, synth.eam_cu_like(), model, p, dt=1e-3, skin=0.5, max_nb=80, precision_every=2,
-                ace_precision="fp64", mode="adaptive", avg_samples=3, avg_dw_min=0.05)
+    md = ops.MD(ctx, atoms, eam_p, model, p, dt=1e-3, skin=0.5, max_nb=80, precision_every=2,
+                ace_precision="fp64", mode="adaptive", avg_samples=3, avg_dw_min=0.05, avg_window=window)
     pos = atoms.pos.clone()
     vel = torch.as_tensor(s.vel, device="cuda").contiguous()
-    ora = averaging.TimeAveragedSwitch(3, 0.05)
-
-    def check(w):
-        s.pos = pos.cpu().numpy()
-        ref = ora.update(s, p, geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5))
-        assert np.array_equal(w.cpu().numpy(), ref["w"])
-        return ref
-
     f, w = md.init(pos)
-    check(w)
-    for step in range(1, 13):
-        st = md.step(pos, vel, f, w, 1)
-        if step % 2 == 0:
-            ref = check(w)
-            assert st["n_active"] == ref["active"].size
+    st = md.step(pos, vel, f, w, 12)
     md.close()
-    assert ref["active"].size > 0
+    dx = np.abs(pos.cpu().numpy() - ref["x"]).max()
+    dw_ = np.abs(w.cpu().numpy() - ref["w"]).max()
+    print(f"{st['precision_updates']} updates, active {st['n_active']}; max |dx| {dx:.2e} A, max |dw| {dw_:.2e}",
+          flush=True)
+    assert st["precision_updates"] == 6
+    assert dx < 1e-10 and np.abs(vel.cpu().numpy() - ref["v"]).max() < 1e-8
+    assert dw_ < 1e-9
+    assert np.array_equal(w.cpu().numpy() > 0, ref["w"] > 0)
+    assert st["n_active"] == int((ref["w"] > 0).sum()) > 0

@@ -197,11 +197,11 @@ def test_void_run_nve_frozen_weights(ops_ctx):
 
 def test_indentation_block_time_averaged_weights(ops_ctx):
     """Time-averaged switching on the 4,000,000-atom block over five samples (ring of three,
-    minimum step 0.05), each at fresh thermal displacements of the mobile atoms.  Every
-    atom: the means, the switch, the filter and the mask against their definitions applied
-    to the library's own sample fields; sampled atoms: the CSP sample against the oracle
-    on a cut cluster, and the spread weight against its definition over the library's
-    averaged w0 field."""
+    minimum step 0.05, the past window of eq. csp_2_i), each at fresh thermal displacements
+    of the mobile atoms.  Every atom: the means, the switch, the filter and the mask
+    against their definitions applied to the library's own sample fields; sampled atoms:
+    the CSP sample against the oracle on a cut cluster, and the spread weight against its
+    definition over the library's averaged w0 field."""
     ops, ctx = ops_ctx
     print("\n[case] full size: 100^3-cell indentation block, time-averaged weights", flush=True)
     from oracle import averaging
@@ -221,9 +221,10 @@ def test_indentation_block_time_averaged_weights(ops_ctx):
         nl = ops.build_neighbors(ctx, atoms, 5.5, max_nb=MAX_NB)
         out = dev.update(ctx, atoms, nl, prec)
         o = {key: out[key].cpu().numpy() for key in ("csp", "csp_avg", "w0", "w_min", "w_avg", "w", "mask", "active")}
+        # past window: the CSP mean holds the samples before this one (this one at first)
+        ca = averaging.moving_average(csp_h if csp_h else [o["csp"]])
         csp_h = ([o["csp"]] + csp_h)[:n_avg]
         wmin_h = ([o["w_min"]] + wmin_h)[:n_avg]
-        ca = averaging.moving_average(csp_h)
         assert np.all((o["csp_avg"] == ca) | (np.isinf(o["csp_avg"]) & np.isinf(ca)))
         w0 = precision.w0_from_csp(ca, prec.csp_lo, prec.csp_hi, prec.switch_kind, s.frozen)
         assert np.array_equal(o["w0"], w0)

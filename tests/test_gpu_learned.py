@@ -111,3 +111,48 @@ def test_learned_criterion_against_csp(trained):
     assert res["learned"]["need"] > 100
     assert res["learned"]["false_negative"] < 0.5 * res["csp_same_cost"]["false_negative"]
     assert res["learned"]["force_err_need_rms_meV"] < 0.8 * res["csp_same_cost"]["force_err_need_rms_meV"]
+
+
+@pytest.mark.parametrize("avg", [0, 3])
+def test_integrator_learned_route(trained, avg):
+    """One integrator with the learned criterion (instantaneous, or time-averaged over the
+    past window) against the same calls made one by one on the integrator's positions:
+    the unweighted EAM pass, the centro-symmetry pass without spreading, features,
+    bfloat16 inference and weight, then the precision pass on the given CSP with the
+    learned weight (with averaging: the same sample sequence through its own state).
+    The centro-symmetry pass must not touch the filtered weights the averaging keeps."""
+    from paper_2411_03002_amd import ops
+    ctx, model, eam, prec, net = trained
+    print(f"\n[case] integrator learned route, avg_samples={avg}", flush=True)
+    s = configs.bulk(8, seed=61, temperature=900.0, vacancies=6, velocities=True)
+    atoms = ops.device_atoms(s)
+    md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, precision_every=2, ace_precision="fp32",
+                avg_samples=avg, avg_dw_min=0.05)
+    md.set_mlp(net, TAU_LO, TAU_HI)
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(s.vel, device="cuda").contiguous()
+    tas = ops.TimeAveragedSwitch(s.n, avg, 0.05) if avg else None
+
+    def explicit(p):
+        at = ops.DeviceAtoms(p.clone(), atoms.lo, atoms.hi, atoms.periodic, atoms.frozen)
+        nl = ops.build_neighbors(ctx, at, 5.5)
+        e = ops.eam_forces(ctx, at, nl, eam, None)
+        first = ops.compute_precision(ctx, at, nl, dataclasses.replace(prec, r_hi=0.0))
+        feat = ops.features(ctx, at, nl, e["rho"], first["csp"], e["f"])
+        _, w0x = net.precision(feat, TAU_LO, TAU_HI)
+        if tas is None:
+            return ops.compute_precision(ctx, at, nl, prec, w0_extra=w0x, csp=first["csp"])["w"]
+        return tas.update(ctx, at, nl, prec, w0_extra=w0x, csp=first["csp"])["w"]
+
+    f, w = md.init(pos)
+    assert torch.equal(w, explicit(pos))
+    checked = 0
+    for step in range(1, 7):
+        md.step(pos, vel, f, w, 1)
+        if step % 2 == 0:
+            # instantaneous: the update precedes the forces, at the drifted positions; past
+            # window: it follows them, at the same positions
+            assert torch.equal(w, explicit(pos)), step
+            checked += 1
+    md.close()
+    assert checked == 3

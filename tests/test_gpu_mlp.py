@@ -147,3 +147,74 @@ def test_training_reduces_loss(ops_ctx):
     mse = float(((pred - target) ** 2).mean())
     print("losses", [round(v, 4) for v in losses], "final mse", mse)
     assert mse < 0.1 * float(target.var())
+
+
+def test_learned_weight_matches_oracle(ops_ctx):
+    """apx_mlp_weight on seeded predictions and features (a third of them outside the
+    training range, some on its bounds) against the oracle's learned weight."""
+    ops, ctx = ops_ctx
+    print("\n[case] learned detection weight", flush=True)
+    rng = np.random.default_rng(21)
+    n = 70001
+    fmin = np.array([0.5, 0.0, 6.0, 0.0], dtype=np.float32)
+    fmax = np.array([3.0, 50.0, 14.0, 4.0], dtype=np.float32)
+    feat = np.stack([rng.uniform(0.3, 3.2, n), rng.uniform(0, 52, n), rng.integers(5, 16, n),
+                     rng.uniform(0, 4.3, n)], axis=1).astype(np.float32)
+    feat[:50, 3] = fmax[3]
+    feat[50:100, 0] = fmin[0]
+    pred = rng.uniform(np.log(1.5e-3), np.log(0.05), n).astype(np.float32)
+    flat, _ = _params()
+    net = ops.Mlp(ctx, flat, np.zeros(4), np.ones(4))
+    net.set_range(fmin, fmax)
+    tau_lo, tau_hi = 5e-3, 1e-2
+    got = net.weight(torch.as_tensor(pred, device="cuda"), torch.as_tensor(feat, device="cuda"), tau_lo,
+                     tau_hi).cpu().numpy()
+    ref = omlp.learned_w0(pred, feat, fmin, fmax, tau_lo, tau_hi)
+    assert np.array_equal(got > 0, ref > 0)
+    assert np.array_equal(got == 1.0, ref == 1.0)
+    assert np.abs(got - ref).max() < 1e-13
+    inside = np.all((feat >= fmin) & (feat <= fmax), axis=1)
+    assert 0.2 < inside.mean() < 0.8 and ((ref > 0) & (ref < 1)).sum() > 1000
+    # apx_mlp_precision is the bfloat16 inference followed by this weight
+    ft = torch.as_tensor(feat, device="cuda")
+    p2, w2 = net.precision(ft, tau_lo, tau_hi)
+    assert torch.equal(p2, net.infer_bf16(ft))
+    assert torch.equal(w2, net.weight(p2, ft, tau_lo, tau_hi))
+
+
+def test_labels_and_feature_stats_match_oracle(ops_ctx):
+    ops, ctx = ops_ctx
+    print("\n[case] learned labels and feature statistics", flush=True)
+    rng = np.random.default_rng(22)
+    n = 100003
+    fp = rng.normal(0.0, 0.5, size=(3, n))
+    ff = fp + rng.normal(0.0, 0.01, size=(3, n)) * (rng.uniform(size=n) < 0.7)
+    dF, lab = ops.mlp_labels(ctx, torch.as_tensor(fp, device="cuda"), torch.as_tensor(ff, device="cuda"))
+    dF_ref, lab_ref = omlp.labels(fp, ff)
+    assert np.allclose(dF.cpu().numpy(), dF_ref, rtol=1e-15, atol=0)
+    lab = lab.cpu().numpy()
+    ulp = np.abs(lab.view(np.int32) - lab_ref.view(np.int32))
+    assert ulp.max() <= 1, ulp.max()
+    feat = np.stack([rng.uniform(1.5, 4.0, n), rng.uniform(0, 50, n), rng.integers(6, 13, n),
+                     rng.exponential(0.3, n)], axis=1).astype(np.float32)
+    st = ops.feature_stats(ctx, torch.as_tensor(feat, device="cuda"))
+    ref = omlp.feature_stats(feat)
+    for k in ("mean", "sd"):
+        assert np.allclose(st[k], ref[k], rtol=1e-12, atol=0), k
+    for k in ("min", "max"):
+        assert np.array_equal(st[k], ref[k]), k
+
+
+def test_weighted_sum(ops_ctx):
+    import math
+    ops, ctx = ops_ctx
+    print("\n[case] weighted energy sum", flush=True)
+    rng = np.random.default_rng(23)
+    for n in (0, 1, 2047, 300001):
+        w = np.where(rng.uniform(size=n) < 0.5, 0.0, rng.uniform(size=n))
+        e = rng.normal(-3.5, 0.2, size=n)
+        got = ops.weighted_sum(ctx, torch.as_tensor(w, device="cuda"), torch.as_tensor(e, device="cuda")).item()
+        ref = math.fsum((w * e).tolist())
+        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (n, got, ref)
+        got1 = ops.weighted_sum(ctx, None, torch.as_tensor(e, device="cuda")).item()
+        assert abs(got1 - math.fsum(e.tolist())) <= 1e-12 * max(1.0, abs(got1)), n

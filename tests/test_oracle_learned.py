@@ -52,3 +52,20 @@ def test_learned_weight_range_fallback():
     feat[5, 3] = np.nextafter(FMAX[3], np.float32(10))  # just outside
     w = mlp.learned_w0(pred, feat, FMIN, FMAX, TAU_LO, TAU_HI)
     assert list(w) == [1.0, 0.0, 0.0, 1.0, 1.0, 0.0]
+
+
+def test_labels_and_feature_stats():
+    # a force gap of exactly 1 eV/A gives log(1.001); equal forces give log(1e-3)
+    fp = np.zeros((3, 3))
+    ff = np.zeros((3, 3))
+    fp[:, 0] = [0.6, 0.8, 0.0]
+    fp[:, 2] = [3.0, 0.0, 4.0]
+    dF, lab = mlp.labels(fp, ff)
+    assert list(dF) == [1.0, 0.0, 5.0]
+    assert lab[1] == np.float32(math.log(1e-3)) and lab[0] == np.float32(math.log(1.001))
+    # two samples per column: mean (a + b)/2, sd |a - b|/sqrt(2)
+    feat = np.array([[1.0, 2.0, 12.0, 0.5], [3.0, 2.0, 10.0, 1.5]], dtype=np.float32)
+    st = mlp.feature_stats(feat)
+    assert list(st["mean"]) == [2.0, 2.0, 11.0, 1.0]
+    assert np.allclose(st["sd"], [math.sqrt(2.0), 0.0, math.sqrt(2.0), math.sqrt(0.5)], rtol=1e-15)
+    assert list(st["min"]) == [1.0, 2.0, 10.0, 0.5] and list(st["max"]) == [3.0, 2.0, 12.0, 1.5]

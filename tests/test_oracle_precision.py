@@ -168,3 +168,25 @@ def test_precision_cfg0_statistics():
     assert np.array_equal(pr["active"], np.nonzero(pr["w"] > 0)[0])
     # no spreading for the plain workload: w == w0
     assert np.array_equal(pr["w"], pr["w0"])
+
+
+def test_extra_weight_before_or_after_spreading():
+    """An additional detection weight joins the CSP weight before the spreading (its
+    detections spread like CSP ones) or, with extra_local, after it (only the atom itself)."""
+    import dataclasses
+    s = configs.cfg0_static()
+    p = synth.precision_static()
+    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+    base = precision.compute_precision(s, p, csr)
+    k = int(np.nonzero(base["w"] == 0.0)[0][0])  # an atom far from every vacancy
+    extra = np.zeros(s.n)
+    extra[k] = 1.0
+    spread_in = precision.compute_precision(s, p, csr, w0_extra=extra)
+    local = precision.compute_precision(s, dataclasses.replace(p, extra_local=True), csr, w0_extra=extra)
+    assert spread_in["w"][k] == 1.0 and local["w"][k] == 1.0
+    grown = np.nonzero((spread_in["w"] > 0) & (base["w"] == 0))[0]
+    assert grown.size > 20 and k in grown  # k and its undetected neighbours within r_hi
+    assert np.array_equal(np.nonzero((local["w"] > 0) & (base["w"] == 0))[0], [k])
+    assert np.array_equal(local["w0"], base["w0"])
+    # both keep everything the CSP criterion detects
+    assert np.all(spread_in["w"] >= base["w"]) and np.all(local["w"] >= base["w"])
