@@ -33,6 +33,21 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
+# Algorithmic work of the product basis per evaluated atom: the nonzero real Gaunt entries
+# of the direct B3 contraction sum_m G A A A (B1 and B2 add under 1 %).  The energy costs
+# about 6 flops per entry, the adjoint about 10 (the three factors' adjoints).  The library
+# recouples the triples through pair couplings and executes fewer flops than this count
+# (kernel_models gives the executed count next to it).
+GAUNT_TERMS = {(10, 4): 211610, (8, 3): 33168}
+ALGO_FLOP_PER_TERM = {"ace.energy": 6.0, "ace.adjoint": 10.0}
+
+# Hardware counters of the dominant kernel class on the indentation block (rocprofv3
+# --pmc FETCH_SIZE, then WRITE_SIZE, KiB per dispatch summed over the launches of one
+# step), scaled to bytes by a 1 GiB device copy (fetch x2.0, write x1.0).  They hold only
+# for the kernel source they were measured on: ``source_sha256`` is checked at run time
+# and the traffic is reported as null when the source has changed since.
+COUNTERS = {}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -46,6 +61,10 @@ def parse():
     ap.add_argument("--no-avg", action="store_true", help="skip the time-averaged-weights run")
     ap.add_argument("--no-eam2", action="store_true", help="skip the EAM2 timing")
     ap.add_argument("--no-hyb2", action="store_true", help="skip the Hyb2 run")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64-ACE adaptive run")
+    ap.add_argument("--no-thermostat", action="store_true", help="skip the local-thermostat run")
+    ap.add_argument("--no-void", action="store_true", help="skip the void-run section")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator section")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the adaptive timed region (for external profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -53,6 +72,10 @@ def parse():
     ap.add_argument("--learned", action="store_true",
                     help="the learned-indicator workload instead: train on 200 snapshots, deploy in the void run")
     return ap.parse_args()
+
+
+THERMAL_STEPS = 400     # fs of the fast potential that bring the block from 600 K velocities to about 300 K
+THERMO_R_OMEGA = 13.5   # A: about 870 mobile atoms in the bulk, of which 799 are drawn
 
 
 def log(msg):
@@ -101,69 +124,241 @@ def kernel_models(stats, n, n_act, nb_avg, nb_act_avg, avg_samples=1):
     }
 
 
-def roofline_for(name, model, launches, total_ms):
+def _source_sha(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_for(name, launches_per_step):
+    """HBM bytes per launch of ``name`` from the committed counter readings, or None when
+    there are none or the kernel source changed after they were taken."""
+    c = COUNTERS.get(name)
+    if not c or _source_sha(c["source"]) != c["source_sha256"]:
+        return None
+    return (2.0 * c["fetch_kib"] + 1.0 * c["write_kib"]) * 1024.0 / max(launches_per_step, 1)
+
+
+def roofline_for(name, model, launches, total_ms, algo=None, launches_per_step=1):
+    """Roofline entry of one kernel class from its measured average launch time.
+
+    ``model`` = (bound, amount per launch, unit) as implemented; ``algo`` (optional) the
+    algorithmic amount per launch that the achieved rate is quoted on (the executed one is
+    reported next to it)."""
     bound, amount, unit = model
     avg_s = total_ms / 1e3 / max(launches, 1)
     if unit == "byte":
         achieved = amount / avg_s / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_ms": avg_s * 1e3,
-                "work_per_launch": amount}
-    achieved = amount / avg_s / 1e12
-    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "avg_ms": avg_s * 1e3,
-            "work_per_launch": amount}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name, launches_per_step),
+                "avg_ms": avg_s * 1e3, "work_per_launch": amount}
+    work = amount if algo is None else algo
+    achieved = work / avg_s / 1e12
+    out = {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_for(name, launches_per_step),
+           "avg_ms": avg_s * 1e3, "work_per_launch": work}
+    if algo is not None:
+        ex = amount / avg_s / 1e12
+        out["executed"] = {"achieved": ex, "frac": ex / PEAK_FP32_TFLOPS, "work_per_launch": amount,
+                           "frac_of_unpacked_fp32": ex / (PEAK_FP32_TFLOPS / 2)}
+    return out
 
 
-def cpu_baseline(sample_cells=(8, 8, 100), budget_s=30.0):
-    """The oracle timed on a column of the same workload: full height, small x/y extent.
+def algo_work(name, n_act, nm_lm=(10, 4)):
+    """Algorithmic flops per launch of the ACE product kernels (None for the others)."""
+    if name in ALGO_FLOP_PER_TERM:
+        return n_act * GAUNT_TERMS[nm_lm] * ALGO_FLOP_PER_TERM[name]
+    return None
 
-    The column keeps the layer structure (free top surface, frozen bottom planes), so
-    its detected fraction matches the full block.  One step of the oracle = precision
-    (CSP, switch, spreading) + hybrid energy and forces (EAM everywhere, ACE on w > 0).
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample_cells=(8, 8, 100)):
+    """The oracle timed on the host: a bounded sample of each workload.
+
+    * value: one adaptive evaluation (neighbours, CSP, spreading, EAM everywhere, ACE on
+      the detected atoms) of a full-height column of the indentation block; the column keeps
+      the layer structure (free top surface, frozen bottom planes), so its detected
+      fraction matches the block's;
+    * void run: one adaptive evaluation of the whole 130,445-atom void run, and the
+      full-ACE rate per atom measured on a 6^3-cell thermal crystal (864 atoms),
+      extrapolated to the void run.
+    The oracle's CSP and spreading loops run on one thread, its tensor operations on
+    ``cores`` threads.
     """
     import torch
     import synth
     from synth import configs
     from oracle import ace as oace
     from oracle import geometry, hybrid, precision
-    nx, ny, nz = sample_cells
-    s = configs.slab100(nx, ny, nz, seed=configs.SEED0 + 2, temperature=300.0)
     prm = synth.ace_random(10, 4, oace.num_basis(10, 4), seed=4242, anchored=True)
+    eam = synth.eam_cu_like()
+
+    def adaptive(s):
+        t0 = time.perf_counter()
+        csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
+        pr = precision.compute_precision(s, synth.precision_hyb1(), csr)
+        hybrid.evaluate(s, eam, prm, pr["w"], csr)
+        return time.perf_counter() - t0, int(pr["active"].size)
+
+    nx, ny, nz = sample_cells
+    col = configs.slab100(nx, ny, nz, seed=configs.SEED0 + 2, temperature=300.0)
+    dt_col, act_col = adaptive(col)
+    void = configs.cfg1()
+    dt_void, act_void = adaptive(void)
+    small = configs.bulk(6, configs.SEED0 + 1, temperature=300.0)
     t0 = time.perf_counter()
-    csr = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, 5.5)
-    pr = precision.compute_precision(s, synth.precision_hyb1(), csr)
-    ev = hybrid.evaluate(s, synth.eam_cu_like(), prm, pr["w"], csr)
-    dt = time.perf_counter() - t0
-    return {"value": s.n / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+    hybrid.evaluate(small, eam, prm, np.ones(small.n))
+    dt_full = time.perf_counter() - t0
+    return {"value": col.n / dt_col, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"one adaptive force evaluation (neighbours, CSP, spreading, EAM, ACE n_max 10 l_max 4 "
-                      f"on {int(pr['active'].size)} detected atoms) of a {nx}x{ny}x{nz}-cell column "
-                      f"({s.n} atoms) of the indentation block, {dt:.1f} s",
-            "active_fraction": float(pr["active"].size) / s.n, "seconds": dt}
+                      f"on {act_col} detected atoms) of a {nx}x{ny}x{nz}-cell column ({col.n} atoms) of the "
+                      f"indentation block, {dt_col:.1f} s",
+            "active_fraction": act_col / col.n, "seconds": dt_col,
+            "host": {"os_cpu_count": os.cpu_count(), "cpu_model": _cpu_model(),
+                     "torch_threads": torch.get_num_threads()},
+            "void_run_adaptive": {"value": void.n / dt_void, "unit": "atom-steps/s", "seconds": dt_void,
+                                  "atoms": void.n, "active": act_void},
+            "void_run_full_ace_extrapolated": {
+                "value": small.n / dt_full, "unit": "atom-steps/s", "seconds": dt_full,
+                "sample": f"full ACE on a 6^3-cell thermal crystal ({small.n} atoms); the per-atom rate applies to "
+                          f"the void run's {void.n} atoms (extrapolated)"}}
 
 
-def run_learned(args):
-    """Learned precision indicator: 200 method-generated 16,384-atom snapshots (bulk, 1 %
-    vacancies, 8 A void, (100) slab, thermalised at 300-1200 K by 500 steps of the fast
-    potential from Maxwell velocities at twice the temperature; 180 train / 20
-    validation), 20 epochs of
-    Adam (batch 4096, lr 1e-3) with the library's kernels, then the 130,445-atom void run
-    (100 steps, weights every 10) with the centro-symmetry criterion and with the learned
-    criterion: atom-steps/s of each, and misassigned atoms and force errors of both
-    criteria on the same configuration (the state after the centro-symmetry run)."""
+def thermal_start(ctx, s, eam, steps):
+    """Positions and velocities after ``steps`` fs of the fast potential alone (no
+    indenter) from the state ``s``: Maxwell velocities at twice the target temperature on
+    the lattice relax to about the target by equipartition."""
+    import torch
+    from paper_2411_03002_amd import ops
+    atoms = ops.device_atoms(s)
+    md = ops.MD(ctx, atoms, eam, None, None, dt=1e-3, mode="eam", precision_every=0)
+    pos = atoms.pos.clone()
+    vel = torch.as_tensor(s.vel, dtype=torch.float64, device=pos.device).contiguous()
+    f, w = md.init(pos)
+    md.step(pos, vel, f, w, steps)
+    md.close()
+    torch.cuda.synchronize()
+    return ops.DeviceAtoms(pos, atoms.lo, atoms.hi, atoms.periodic, atoms.frozen), vel
+
+
+def void_run(ctx, K=100, every=10, checkpoints=(0, 50, 100)):
+    """The void run (32^3 cells, 12-A void, 300 K Maxwell on the lattice, Hyb1 weights every
+    10 steps, float32 ACE): adaptive and full-ACE atom-steps/s over K NVE steps, and along
+    the adaptive trajectory at the checkpoint steps the float32-vs-float64 ACE force error
+    and the method error (hybrid vs full ACE, both float64) on the atoms with w = 1 and on
+    all atoms (per component, rms and max, meV/A)."""
+    import torch
+    import synth
+    from synth import configs
+    from paper_2411_03002_amd import ops
+    s = configs.cfg1()
+    n = s.n
+    model = ops.AceModel(ctx, synth.ace_random(10, 4, ops.num_basis(10, 4), seed=4242, anchored=True))
+    eam, prec = synth.eam_cu_like(), synth.precision_hyb1()
+    atoms = ops.device_atoms(s)
+    vel0 = torch.as_tensor(s.vel, dtype=torch.float64, device="cuda").contiguous()
+    out = {"workload": f"void run 32^3 FCC cells, {n} atoms, 12 A void, 300 K, Hyb1 every {every} steps, "
+                       f"float32 ACE (10, 4)", "atoms": n, "steps": K}
+    for mode in ("adaptive", "full_ace"):
+        md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, precision_every=every, ace_precision="fp32", mode=mode)
+        pos, vel = atoms.pos.clone(), vel0.clone()
+        f, w = md.init(pos)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = md.step(pos, vel, f, w, K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        md.close()
+        out[mode] = {"atom_steps_per_s": n * K / dt, "ms_per_step": dt / K * 1e3,
+                     "ace_atoms_mean": st["ace_atoms"] / K}
+    out["adaptive_over_full_ace"] = out["adaptive"]["atom_steps_per_s"] / out["full_ace"]["atom_steps_per_s"]
+    everyone = torch.arange(n, dtype=torch.int32, device="cuda")
+
+    def stats(d, sel):
+        d = d[:, sel]
+        if d.numel() == 0:
+            return {"rms": 0.0, "max": 0.0, "atoms": 0}
+        return {"rms": float(d.pow(2).mean().sqrt().item() * 1e3), "max": float(d.abs().max().item() * 1e3),
+                "atoms": int(sel.sum().item())}
+
+    errs = []
+    md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, precision_every=every, ace_precision="fp32")
+    pos, vel = atoms.pos.clone(), vel0.clone()
+    f, w = md.init(pos)
+    done = 0
+    for c in checkpoints:
+        if c > done:
+            md.step(pos, vel, f, w, c - done)
+            done = c
+        at = ops.DeviceAtoms(pos, atoms.lo, atoms.hi, atoms.periodic, atoms.frozen)
+        nl = ops.build_neighbors(ctx, at, 5.5)
+        active = torch.nonzero(w > 0).flatten().to(torch.int32)
+        a64 = ops.ace_energy_forces(ctx, at, nl, model, active, w, "fp64")
+        a32 = ops.ace_energy_forces(ctx, at, nl, model, active, w, "fp32")
+        e = ops.eam_forces(ctx, at, nl, eam, w)
+        full = ops.ace_energy_forces(ctx, at, nl, model, everyone, None, "fp64")
+        one = w == 1.0
+        every_atom = torch.ones_like(one)
+        errs.append({"step": c, "w_eq_1": int(one.sum().item()), "w_gt_0": int((w > 0).sum().item()),
+                     "fp32_vs_fp64": {"active": stats(a32["f"] - a64["f"], w > 0),
+                                      "all": stats(a32["f"] - a64["f"], every_atom)},
+                     "hybrid_vs_full_ace": {"w_eq_1": stats(e["f"] + a64["f"] - full["f"], one),
+                                            "all": stats(e["f"] + a64["f"] - full["f"], every_atom)}})
+        del nl, a64, a32, e, full
+    md.close()
+    out["errors_meV_per_A"] = errs
+    del model
+    torch.cuda.empty_cache()
+    return out
+
+
+def learned_section(steps=100, snapshots=200, log_fn=None):
+    """Learned precision indicator (4-64-64-64-1 network on [rho_EAM, min(CSP, 50),
+    coordination, |F_EAM|] predicting log(|F_ACE - F_EAM| + 1e-3)).
+
+    Training: ``snapshots`` method-generated 16,384-atom snapshots (bulk, 1 % vacancies,
+    8-A void, (100) slab; thermalised at 300-1200 K by 500 fs of the fast potential from
+    Maxwell velocities at twice the temperature; 90 % train / 10 % validation), 20 epochs of
+    Adam (batch 4096, lr 1e-3) with the library's kernels.  The decision thresholds on the
+    predicted gap are the budget's (5 / 10 meV/A) lowered by exp(-sigma), sigma the rms
+    validation residual of the predicted log-gap, so that an atom whose prediction is one
+    residual low is still taken.
+
+    Deployment, the void run (32^3 cells, 12-A void) thermalised at 300 K and at 900 K:
+    * 300 K, Hyb1 as configured: the centro-symmetry criterion with its 4/12-A spreading,
+      against the same plus the learned weight joined after the spreading (learned
+      detections take ACE themselves, APX_PREC_EXTRA_LOCAL), and against the
+      centro-symmetry criterion with its threshold lowered to the same number of ACE atoms;
+      atom-steps/s of the first two over ``steps`` steps with weights every 10 steps.
+    * 900 K, no spreading for any criterion (at this temperature the 12-A spreading of the
+      thermal detections covers the box): the selections themselves at equal cost.
+    Each criterion: atoms that need the precise potential (|F_ACE - F_EAM| > 10 meV/A),
+    false negatives and positives, rms hybrid force error on the needing atoms."""
+    import dataclasses
     import torch
     import synth
     from synth import configs
     from paper_2411_03002_amd import learned, ops
 
-    tau_lo, tau_hi = 5e-3, 1e-2
+    lg = log_fn or (lambda m: None)
     ctx = ops.Context(0)
     eam = synth.eam_cu_like()
     model = ops.AceModel(ctx, synth.ace_label_model(ops.num_basis(10, 4)))
     prec = synth.precision_hyb1()
+    tau_lo, tau_hi = 5e-3, 1e-2
     t0 = time.perf_counter()
     feats, labels = [], []
-    for k in range(200):
+    for k in range(snapshots):
         start = configs.cfg4_snapshot(k)
         atoms_k = learned.thermalize(ctx, start, eam, start.meta["md_steps"])
         snap = learned.snapshot(ctx, atoms_k, eam, model, prec, "fp32")
@@ -171,65 +366,109 @@ def run_learned(args):
         labels.append(snap.label)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    tr_f, tr_y = torch.cat(feats[:180]), torch.cat(labels[:180])
-    va_f, va_y = torch.cat(feats[180:]), torch.cat(labels[180:])
-    log(f"{tr_f.shape[0]} training and {va_f.shape[0]} validation samples in {t_data:.1f} s")
+    n_tr = snapshots - max(1, snapshots // 10)
+    tr_f, tr_y = torch.cat(feats[:n_tr]), torch.cat(labels[:n_tr])
+    va_f, va_y = torch.cat(feats[n_tr:]), torch.cat(labels[n_tr:])
+    del feats, labels
+    lg(f"learned: {tr_f.shape[0]} training and {va_f.shape[0]} validation samples in {t_data:.1f} s")
     t0 = time.perf_counter()
     net = learned.train(ctx, tr_f, tr_y, epochs=20, batch=4096, lr=1e-3, seed=0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    r_val = float(torch.corrcoef(torch.stack([net.infer_bf16(va_f), va_y]))[0, 1].item())
-    log(f"trained in {t_train:.1f} s, validation correlation (bf16 inference) {r_val:.3f}")
+    _, loss = net.gradients(va_f, va_y)
+    sigma = math.sqrt(float(loss.item()))
+    cal = math.exp(-sigma)
+    t_lo, t_hi = tau_lo * cal, tau_hi * cal
+    lg(f"learned: trained in {t_train:.1f} s, validation residual {sigma:.3f} (log units), "
+       f"thresholds {t_lo * 1e3:.2f}/{t_hi * 1e3:.2f} meV/A")
+    out = {"training": {"samples": int(tr_f.shape[0]), "validation_samples": int(va_f.shape[0]),
+                        "data_seconds": t_data, "train_seconds": t_train, "validation_rms_residual": sigma,
+                        "thresholds_meV_per_A": [t_lo * 1e3, t_hi * 1e3]}}
+    del tr_f, tr_y, va_f, va_y
 
-    s = configs.cfg1()
-    atoms = ops.device_atoms(s)
-    vel0 = torch.as_tensor(s.vel, device="cuda").contiguous()
-    K, W = args.steps, args.warmup
-    runs = {}
+    def state(T):
+        s = configs.bulk(32, configs.SEED0 + 1, temperature=2 * T, void_radius=12.0, velocities=True, sigma=0.0)
+        atoms, vel = thermal_start(ctx, s, eam, 500)
+        return atoms, vel
+
+    def assess_all(atoms, criteria):
+        nl = ops.build_neighbors(ctx, atoms, 5.5)
+        everyone = torch.arange(atoms.n, dtype=torch.int32, device="cuda")
+        f_ace = ops.ace_energy_forces(ctx, atoms, nl, model, everyone, None, "fp64")["f"]
+        dF, _ = ops.mlp_labels(ctx, f_ace, ops.eam_forces(ctx, atoms, nl, eam, None)["f"])
+        res = {}
+        for name, pr in criteria(nl).items():
+            e = ops.eam_forces(ctx, atoms, nl, eam, pr["w"])
+            a = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp64")
+            res[name] = learned.assess(pr["w"], dF, e["f"] + a["f"], f_ace, tau_lo, tau_hi)
+        return res
+
+    def same_cost(atoms, nl, p, target):
+        # the centro-symmetry threshold (switch width kept) that reaches `target` ACE atoms
+        lo, hi = 0.0, p.csp_lo
+        best = None
+        for _ in range(40):
+            mid = 0.5 * (lo + hi)
+            pr = ops.compute_precision(ctx, atoms, nl, dataclasses.replace(p, csp_lo=mid, csp_hi=mid + 0.5))
+            if pr["n_active"] >= target:
+                best, lo = pr, mid
+            else:
+                hi = mid
+        return best
+
+    # 300 K: Hyb1 with spreading; learned detections joined after the spreading
+    atoms, vel0 = state(300.0)
+    local = dataclasses.replace(prec, extra_local=True)
+
+    def crit300(nl):
+        csp = ops.compute_precision(ctx, atoms, nl, prec)
+        lrn = learned.weights(ctx, atoms, nl, local, eam, net, t_lo, t_hi)
+        return {"csp": csp, "learned": lrn, "csp_same_cost": same_cost(atoms, nl, prec, lrn["n_active"])}
+
+    dep = {"temperature": 300.0, "atoms": atoms.n, "assessment": assess_all(atoms, crit300)}
     for name in ("csp", "learned"):
-        md = ops.MD(ctx, atoms, eam, model, prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
-                    ace_precision="fp32", mode="adaptive")
+        md = ops.MD(ctx, atoms, eam, model, local, dt=1e-3, precision_every=10, ace_precision="fp32")
         if name == "learned":
-            md.set_mlp(net, tau_lo, tau_hi)
+            md.set_mlp(net, t_lo, t_hi)
         pos, vel = atoms.pos.clone(), vel0.clone()
         f, w = md.init(pos)
-        if W:
-            md.step(pos, vel, f, w, W)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = md.step(pos, vel, f, w, K)
+        st = md.step(pos, vel, f, w, steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         md.close()
-        runs[name] = {"atom_steps_per_s": s.n * K / dt, "ms_per_step": dt / K * 1e3,
-                      "active_mean": st["ace_atoms"] / K, "pos": pos}
-        log(f"{name}: {dt / K * 1e3:.3f} ms/step, mean detected {st['ace_atoms'] / K:.0f}")
-    # both criteria on the configuration the centro-symmetry run ended in
-    at = ops.DeviceAtoms(runs["csp"]["pos"], atoms.lo, atoms.hi, atoms.periodic, atoms.frozen)
-    nl = ops.build_neighbors(ctx, at, 5.5)
-    everyone = torch.arange(s.n, dtype=torch.int32, device="cuda")
-    f_ace = ops.ace_energy_forces(ctx, at, nl, model, everyone, None, "fp64")["f"]
-    dF = (f_ace - ops.eam_forces(ctx, at, nl, eam, None)["f"]).norm(dim=0)
-    assess = {}
-    for name, use in (("csp", None), ("learned", net)):
-        pr = learned.weights(ctx, at, nl, prec, eam, use, tau_lo, tau_hi)
-        e = ops.eam_forces(ctx, at, nl, eam, pr["w"])
-        a = ops.ace_energy_forces(ctx, at, nl, model, pr["active"], pr["w"], "fp64")
-        assess[name] = learned.assess(pr["w"], dF, e["f"] + a["f"], f_ace, tau_lo, tau_hi)
-    result = {
-        "metric": "learned vs CSP criterion: atom-steps/s and misassigned-atom force error", "unit": "atom-steps/s",
-        "value": runs["learned"]["atom_steps_per_s"], "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": runs["learned"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 ACE / f64 EAM; bf16 network inference", "data": "synthetic",
-        "config": {"workload": f"void run 32^3 FCC cells ({s.n} atoms, 12 A void, 300 K), label ACE "
-                               f"(n_max 10, l_max 4), Hyb1 detection every 10 steps; network trained on "
-                               f"200 x 16,384-atom snapshots", "atoms": s.n},
-        "training": {"samples": int(tr_f.shape[0]), "validation_samples": int(va_f.shape[0]),
-                     "data_seconds": t_data, "train_seconds": t_train, "validation_r_bf16": r_val},
-        "csp": {k: v for k, v in runs["csp"].items() if k != "pos"} | {"assessment": assess["csp"]},
-        "learned": {k: v for k, v in runs["learned"].items() if k != "pos"} | {"assessment": assess["learned"]},
-    }
+        dep[name] = {"atom_steps_per_s": atoms.n * steps / dt, "ms_per_step": dt / steps * 1e3,
+                     "ace_atoms_mean": st["ace_atoms"] / steps}
+    out["void_300K_hyb1"] = dep
+    lg(f"learned 300 K: " + ", ".join(f"{k} active {v['active']} FN {v['false_negative']} "
+                                        f"err {v['force_err_need_rms_meV']:.2f}" for k, v in dep["assessment"].items()))
+    # 900 K, no spreading: the selections themselves
+    atoms, _ = state(900.0)
+    nospread = dataclasses.replace(prec, r_hi=0.0, extra_local=True)
+
+    def crit900(nl):
+        csp = ops.compute_precision(ctx, atoms, nl, nospread)
+        lrn = learned.weights(ctx, atoms, nl, nospread, eam, net, t_lo, t_hi)
+        return {"csp": csp, "learned": lrn, "csp_same_cost": same_cost(atoms, nl, nospread, lrn["n_active"])}
+
+    out["void_900K_local"] = {"temperature": 900.0, "atoms": atoms.n, "assessment": assess_all(atoms, crit900)}
+    lg(f"learned 900 K: " + ", ".join(f"{k} active {v['active']} FN {v['false_negative']} "
+                                        f"err {v['force_err_need_rms_meV']:.2f}"
+                                        for k, v in out["void_900K_local"]["assessment"].items()))
+    del model, net
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_learned(args):
+    result = {"metric": "learned vs CSP criterion: misassigned-atom force error and atom-steps/s",
+              "data": "synthetic", "learned": learned_section(args.steps, log_fn=log)}
     print(json.dumps(result), flush=True)
+
+
+def class_times(tim, K):
+    return dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick+thermostat"], [t / K for t in tim]))
 
 
 def main():
@@ -257,23 +496,25 @@ def main():
     K, W = args.steps, args.warmup
     KF = args.full_steps if args.full_steps is not None else K
     cells = args.cells
-    log(f"building {cells}^3-cell indentation block")
-    s = configs.cfg2(cells=cells)
+    ctx = ops.Context(0)
+    eam_p = synth.eam_cu_like()
+    log(f"building {cells}^3-cell indentation block, thermal start ({THERMAL_STEPS} fs of the fast potential "
+        f"from 600 K velocities)")
+    s = configs.cfg2(cells=cells, temperature=600.0)
     ind = s.meta["indenter"]
     n = s.n
+    atoms, vel0 = thermal_start(ctx, s, eam_p, THERMAL_STEPS)
     nb = ops.num_basis(10, 4)
     prm = synth.ace_random(10, 4, nb, seed=4242, anchored=True)
-    eam_p = synth.eam_cu_like()
     prec = synth.precision_hyb1()
-    ctx = ops.Context(0)
-    atoms = ops.device_atoms(s)
     model = ops.AceModel(ctx, prm)
     stats = model.stats()
-    vel0 = torch.as_tensor(s.vel, dtype=torch.float64, device="cuda").contiguous()
 
-    def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0, prec_set=None):
+    def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0, prec_set=None, ace_precision="fp32",
+            thermostat=None):
         md = ops.MD(ctx, atoms, eam_p, model, prec_set or prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
-                    ace_precision="fp32", mode=mode, indenter=ind, avg_samples=avg_samples, avg_dw_min=avg_dw_min)
+                    ace_precision=ace_precision, mode=mode, indenter=ind, avg_samples=avg_samples,
+                    avg_dw_min=avg_dw_min, thermostat=thermostat)
         pos = atoms.pos.clone()
         vel = vel0.clone()
         f, w = md.init(pos)
@@ -302,33 +543,35 @@ def main():
         "ms_per_step": dt_a / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 ACE / f64 EAM, neighbours, integration", "data": "synthetic",
         "config": {"workload": f"nanoindentation block {cells}^3 FCC cells, {n} atoms, x/y periodic, free z, "
-                               f"3 frozen (002) planes, indenter R 40 A K 10 eV/A^3 0.2 A/ps, 300 K, "
-                               f"anchored ACE n_max 10 l_max 4 (float32), Hyb1 detection every 10 steps",
+                               f"3 frozen (002) planes, indenter R 40 A K 10 eV/A^3 0.2 A/ps, 300 K (thermal start: "
+                               f"{THERMAL_STEPS} fs of the fast potential from 600 K Maxwell velocities), anchored "
+                               f"ACE n_max 10 l_max 4 (float32), Hyb1 detection every 10 steps",
                    "atoms": n, "dt_fs": 1.0, "precision_every": 10},
         "active_atoms": int(st_a["n_active"]), "active_fraction": st_a["n_active"] / n,
         "active_atoms_mean": st_a["ace_atoms"] / K,
         "rebuilds": int(st_a["rebuilds"]),
-        "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
-                                      [t / K for t in tim_a])),
+        "class_ms_per_step": class_times(tim_a, K),
     }
     if args.profile_only:
         print(json.dumps(result), flush=True)
         return
     # live per-kernel roofline of the adaptive timed region
     nb_avg = 60.0
+    n_act = st_a["ace_atoms"] / K
     # ACE work per launch: the mean number of atoms ACE was evaluated for over the timed
     # steps (the detected set changes at every weight update)
-    models = kernel_models(stats, n, st_a["ace_atoms"] / K, nb_avg, 42.0)
+    models = kernel_models(stats, n, n_act, nb_avg, 42.0)
     kern = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_a.items()}
     dom = max(prof_a.items(), key=lambda kv: kv[1][1])[0]
     result["kernels"] = kern
     result["dominant_kernel"] = dom
-    roofs = {k: roofline_for(k, models[k], *prof_a[k]) for k in prof_a if k in models}
+    roofs = {k: roofline_for(k, models[k], *prof_a[k], algo=algo_work(k, n_act)) for k in prof_a if k in models}
     result["roofline"] = roofs.get(dom)
     result["roofline_all"] = roofs
 
-    # force error of float32 ACE against float64 on the detected atoms at the start
-    log("float32 vs float64 ACE forces on the detected atoms")
+    # float32 vs float64 ACE on the detected atoms, and the method error (hybrid vs full
+    # ACE, both float64) on the atoms with w = 1, at the thermal start
+    log("force errors at the start: float32 vs float64 ACE, hybrid vs full ACE")
     nl = ops.build_neighbors(ctx, atoms, 5.5, max_nb=80)
     pr = ops.compute_precision(ctx, atoms, nl, prec)
     a64 = ops.ace_energy_forces(ctx, atoms, nl, model, pr["active"], pr["w"], "fp64")
@@ -339,37 +582,70 @@ def main():
     result["force_err_fp32_vs_fp64_meV_per_A"] = {
         "max": float(dd.max().item() * 1e3), "rms": float(dd.pow(2).mean().sqrt().item() * 1e3),
         "atoms": int(wmask.sum().item())}
-    del nl, a64, a32, d, dd
+    del a32, d, dd
+    e_hyb = ops.eam_forces(ctx, atoms, nl, eam_p, pr["w"])
+    everyone = torch.arange(n, dtype=torch.int32, device="cuda")
+    full = ops.ace_energy_forces(ctx, atoms, nl, model, everyone, None, "fp64")
+    diff = e_hyb["f"] + a64["f"] - full["f"]
+    one = pr["w"] == 1.0
+    mobile = torch.ones(n, dtype=torch.bool, device="cuda") if atoms.frozen is None else atoms.frozen == 0
+    result["method_err_hybrid_vs_full_ace_meV_per_A"] = {
+        "w_eq_1": {"rms": float(diff[:, one].pow(2).mean().sqrt().item() * 1e3),
+                   "max": float(diff[:, one].abs().max().item() * 1e3), "atoms": int(one.sum().item())},
+        "mobile": {"rms": float(diff[:, mobile].pow(2).mean().sqrt().item() * 1e3),
+                   "max": float(diff[:, mobile].abs().max().item() * 1e3), "atoms": int(mobile.sum().item())}}
+    del nl, a64, e_hyb, full, diff
     torch.cuda.empty_cache()
+
+    if not args.no_fp64:
+        log(f"adaptive with float64 ACE: {W} warm-up + {K} timed steps")
+        dt_d, st_d, _, tim_d = run("adaptive", K, W, False, ace_precision="fp64")
+        result["fp64_ace"] = {"atom_steps_per_s": n * K / dt_d, "ms_per_step": dt_d / K * 1e3,
+                              "active_atoms_mean": st_d["ace_atoms"] / K, "class_ms_per_step": class_times(tim_d, K)}
+        log(f"float64 ACE {dt_d / K * 1e3:.3f} ms/step")
 
     if not args.no_avg:
         # the paper's time-averaged switching: a 110-fs window, here 11 samples at one
-        # weight update per 10 steps, minimum step 1/11; warm-up until the rings are full
-        na, wa = 11, 10 * 11
+        # weight update per 10 steps, minimum step 1/11, the past window; warm-up until both
+        # rings hold samples formed from full CSP means (2 N updates)
+        na, wa = 11, 2 * 10 * 11 + 10
         log(f"time-averaged weights ({na} samples): {wa} warm-up + {K} timed steps")
         dt_t, st_t, prof_t, tim_t = run("adaptive", K, wa, True, avg_samples=na, avg_dw_min=1.0 / na)
         models_t = kernel_models(stats, n, st_t["ace_atoms"] / K, nb_avg, 42.0, avg_samples=na)
         result["time_averaged"] = {
-            "avg_samples": na, "window_fs": 10 * na, "dw_min": 1.0 / na, "warmup": wa,
+            "avg_samples": na, "window_fs": 10 * na, "dw_min": 1.0 / na, "warmup": wa, "window": "past",
             "atom_steps_per_s": n * K / dt_t, "ms_per_step": dt_t / K * 1e3,
             "active_atoms": int(st_t["n_active"]), "active_atoms_mean": st_t["ace_atoms"] / K,
-            "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
-                                          [t / K for t in tim_t])),
+            "class_ms_per_step": class_times(tim_t, K),
             "kernels": {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
                         for k, v in prof_t.items() if k.startswith("prec.")},
             "roofline": {k: roofline_for(k, models_t[k], *prof_t[k]) for k in ("prec.avg_csp", "prec.avg_w")
                          if k in prof_t},
         }
         log(f"time-averaged {dt_t / K * 1e3:.3f} ms/step, active mean {st_t['ace_atoms'] / K:.0f}")
+        if not args.no_thermostat:
+            th = dict(r_omega=THERMO_R_OMEGA, omega_max=800, seed=2024)
+            log(f"time-averaged weights with the local thermostat (|Omega| 800, r_omega {THERMO_R_OMEGA} A): "
+                f"{wa} warm-up + {K} timed steps")
+            dt_h, st_h, prof_h, tim_h = run("adaptive", K, wa, True, avg_samples=na, avg_dw_min=1.0 / na,
+                                            thermostat=th)
+            result["thermostat"] = {
+                "omega_max": 800, "r_omega": THERMO_R_OMEGA, "atom_steps_per_s": n * K / dt_h,
+                "ms_per_step": dt_h / K * 1e3, "corrected_steps": int(st_h["thermo_steps"]),
+                "corrections": int(st_h["thermo_corrected"]), "failed": int(st_h["thermo_failed"]),
+                "class_ms_per_step": class_times(tim_h, K),
+                "kernels": {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
+                            for k, v in prof_h.items() if k.startswith("thermo.") or k == "eam.force_delta"},
+            }
+            log(f"thermostat {dt_h / K * 1e3:.3f} ms/step, {st_h['thermo_corrected']} corrections over "
+                f"{st_h['thermo_steps']} steps")
 
     if not args.no_hyb2:
         # the paper's Hyb2 set: spreading radii 8/20 A instead of 4/12 A
         log(f"Hyb2 weights: {W} warm-up + {K} timed steps")
         dt_h, st_h, prof_h, tim_h = run("adaptive", K, W, False, prec_set=synth.precision_hyb2())
         result["hyb2"] = {"r_lo": 8.0, "r_hi": 20.0, "atom_steps_per_s": n * K / dt_h, "ms_per_step": dt_h / K * 1e3,
-                          "active_atoms_mean": st_h["ace_atoms"] / K,
-                          "class_ms_per_step": dict(zip(["drift+neighbours", "precision", "eam", "ace", "blend+kick"],
-                                                        [t / K for t in tim_h]))}
+                          "active_atoms_mean": st_h["ace_atoms"] / K, "class_ms_per_step": class_times(tim_h, K)}
         log(f"Hyb2 {dt_h / K * 1e3:.3f} ms/step, active mean {st_h['ace_atoms'] / K:.0f}")
 
     if not args.no_eam2:
@@ -388,7 +664,7 @@ def main():
         ctx.profile(False)
         m6 = kernel_models(stats, n, 0, 78.0, 0.0)
         result["eam2"] = {
-            "potential": "EAM2 copper, refit parameters (Appendix D, Table II)", "r_list": 6.0,
+            "potential": "EAM2 copper, refit parameters (Appendix E, Table III)", "r_list": 6.0,
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_e.items()
                         if k.startswith("eam.")},
             "roofline": {k: roofline_for(k, m6[k], *prof_e[k]) for k in ("eam.density", "eam.force") if k in prof_e},
@@ -404,13 +680,26 @@ def main():
         result["full_ace_atom_steps_per_s"] = full
         result["full_ace_ms_per_step"] = dt_f / KF * 1e3
         result["adaptive_over_full_ace"] = adaptive / full
-        mf = kernel_models(stats, n, st_f["ace_atoms"] / KF, nb_avg, 42.0)
+        n_f = st_f["ace_atoms"] / KF
+        mf = kernel_models(stats, n, n_f, nb_avg, 42.0)
         for k in ("ace.energy", "ace.adjoint"):
             if k in prof_f:
-                result[f"roofline_full_ace_{k.split('.')[1]}"] = roofline_for(k, mf[k], *prof_f[k])
+                result[f"roofline_full_ace_{k.split('.')[1]}"] = roofline_for(k, mf[k], *prof_f[k],
+                                                                            algo=algo_work(k, n_f))
         result["kernels_full_ace"] = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
                                       for k, v in prof_f.items()}
         log(f"full ACE {dt_f / KF * 1e3:.2f} ms/step, {full:.4g} atom-steps/s, ratio {adaptive / full:.2f}")
+    del model, atoms
+    torch.cuda.empty_cache()
+    if not args.no_void:
+        log("void run: adaptive and full ACE, errors at steps 0/50/100")
+        result["void_run"] = void_run(ctx)
+        v = result["void_run"]
+        log(f"void run adaptive {v['adaptive']['ms_per_step']:.3f} ms/step, full ACE "
+            f"{v['full_ace']['ms_per_step']:.3f} ms/step, ratio {v['adaptive_over_full_ace']:.2f}")
+    if not args.no_learned:
+        log("learned indicator: training on method-generated snapshots, deployment in the void run")
+        result["learned"] = learned_section(log_fn=log)
     if not args.no_cpu:
         log("oracle CPU baseline")
         result["cpu_baseline"] = cpu_baseline()

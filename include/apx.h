@@ -67,6 +67,12 @@ int32_t apx_profile_count(apx_ctx* ctx);
 apx_status apx_profile_entry(apx_ctx* ctx, int32_t k, const char** name, int64_t* launches,
                              double* total_ms);
 
+/* Diagnostic: the FP64 functions the pair loops use, on x [n] (device): exp (Tang's
+ * table-driven method, ACM TOMS 15(2), 1989), 1/x and 1/sqrt(x) (hardware estimates with
+ * two Newton steps).  Outputs (device [n], each nullable). */
+apx_status apx_fp64_functions(apx_ctx* ctx, int64_t n, const double* x, double* exp_out, double* rcp_out,
+                              double* rsq_out);
+
 /* ------------------------------------------------------------------- atoms */
 typedef struct {
   int64_t n;             /* number of atoms */

@@ -96,6 +96,7 @@ PROTOTYPES = {
     "apx_profile_entry": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]),
     "apx_ace_model_stats": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
+    "apx_fp64_functions": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P]),
     "apx_build_neighbors": (C.c_int32, [_P, C.POINTER(Atoms), C.c_double, C.POINTER(NList), C.POINTER(C.c_int32)]),
     "apx_compute_precision": (C.c_int32, [_P, C.POINTER(Atoms), C.POINTER(NList), C.POINTER(PrecParams), _P,
                                           _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),

@@ -51,6 +51,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compiles every source (``incremental``: only those older than their object)."""
     if not (incremental and os.path.exists(os.path.join(CSRC, "ace_coupling_gen.h"))):
         subprocess.run([sys.executable, os.path.join(CSRC, "gen_coupling.py")], check=True)
+        subprocess.run([sys.executable, os.path.join(CSRC, "gen_exp_table.py")], check=True)
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
     workers = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))

@@ -249,11 +249,33 @@ void prof_flush(apx_ctx* ctx, bool wait) {
   ctx->prof_pending.resize(keep);
 }
 
+__global__ void k_fp64_functions(long long n, const double* __restrict__ x, double* __restrict__ e,
+                                 double* __restrict__ rc, double* __restrict__ rs) {
+  __shared__ double etab[32];
+  stage_exp_table(etab);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i];
+  if (e) e[i] = exp_tab(v, etab);
+  if (rc) rc[i] = rcp_nr(v);
+  if (rs) rs[i] = rsq_nr(v);
+}
+
 }  // namespace apx
 
 using namespace apx;
 
 extern "C" {
+
+apx_status apx_fp64_functions(apx_ctx* ctx, int64_t n, const double* x, double* exp_out, double* rcp_out,
+                              double* rsq_out) {
+  if (!ctx) return APX_EINVAL;
+  if (n < 0 || (n > 0 && !x)) return fail(ctx, APX_EINVAL, "x is required");
+  if (n == 0) return APX_OK;
+  k_fp64_functions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, x, exp_out, rcp_out, rsq_out);
+  APX_LAUNCH_CHECK(ctx);
+  return APX_OK;
+}
 
 apx_status apx_profile_enable(apx_ctx* ctx, int32_t on) {
   if (!ctx) return APX_EINVAL;

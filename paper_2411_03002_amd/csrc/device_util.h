@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "exp_table_gen.h"
 
 namespace apx {
 
@@ -52,6 +53,52 @@ __device__ __forceinline__ double fcut_exact(double x) {
   double t3 = 1.25 * x3;
   double t5 = 0.375 * x5;
   return ((1.0 - t1) + t3) - t5;
+}
+
+// ------------------------------------------------------- fast FP64 elementary functions
+// The pair loops evaluate exponentials, reciprocals and square roots per neighbour; these
+// forms give up the last ulp or two for fewer FP64 instructions.
+
+// exp(x) by Tang's table-driven method (ACM TOMS 15(2), 1989) with 32 entries:
+// x = (32 m + j) ln2/32 + r, |r| <= ln2/64 (reduction constant in two parts), and
+// exp(x) = 2^m 2^(j/32) exp(r) with exp(r) - 1 from its Taylor polynomial to degree 6
+// (truncation below 2e-18).  `tab` holds kExp2Table (staged in LDS: the index diverges
+// across lanes).  For x below -708 the result underflows to 0 through the scaling.
+__device__ __forceinline__ double exp_tab(double x, const double* tab) {
+  const double k = rint(x * kInvLn2x32);
+  const double r = fma(-k, kLn2d32Lo, fma(-k, kLn2d32Hi, x));
+  const int ki = (int)k;
+  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = fma(r, p, 1.0 / 24.0);
+  p = fma(r, p, 1.0 / 6.0);
+  p = fma(r, p, 0.5);
+  p = fma(r, p, 1.0);
+  p *= r;
+  const double t = tab[ki & 31];
+  return ldexp(fma(t, p, t), ki >> 5);
+}
+
+// 1/a from the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+
+// 1/sqrt(a) from the hardware estimate refined by two Newton steps y (3 - a y^2)/2.
+__device__ __forceinline__ double rsq_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+// Stages kExp2Table in LDS; every thread of the block must call it before any returns.
+__device__ __forceinline__ void stage_exp_table(double* sh) {
+  if (threadIdx.x < 32) sh[threadIdx.x] = kExp2Table[threadIdx.x];
+  __syncthreads();
 }
 
 template <class T>

@@ -25,7 +25,7 @@ struct EamDev {
 __device__ __forceinline__ void taper(double x, double& p, double& dp) {
   const double x2 = x * x;
   const double x4 = x2 * x2;
-  const double den = 1.0 / (1.0 + x4);
+  const double den = rcp_nr(1.0 + x4);
   p = x4 * den;
   dp = 4.0 * x2 * x * den * den;
 }
@@ -33,8 +33,8 @@ __device__ __forceinline__ void taper(double x, double& p, double& dp) {
 // EAM2 pair functions at r (tapered parts with the taper value ps and slope dps, dps
 // already divided by h): pair potential Phi, density zeta and their derivatives.
 __device__ __forceinline__ void eam2_pair(const EamDev& p, double r, double ps, double dps, double& phi,
-                                          double& dphi, double& rho, double& drho) {
-  const double t1 = exp(-p.alpha1 * (r - p.r01)), t2 = exp(-p.alpha2 * (r - p.r02));
+                                          double& dphi, double& rho, double& drho, const double* etab) {
+  const double t1 = exp_tab(-p.alpha1 * (r - p.r01), etab), t2 = exp_tab(-p.alpha2 * (r - p.r02), etab);
   const double m1 = t1 * t1 - 2.0 * t1, m2 = t2 * t2 - 2.0 * t2;
   const double dm1 = 2.0 * p.alpha1 * (t1 - t1 * t1), dm2 = 2.0 * p.alpha2 * (t2 - t2 * t2);
   const double core = p.E1 * m1 + p.E2 * m2 + p.delta;
@@ -50,11 +50,11 @@ __device__ __forceinline__ void eam2_pair(const EamDev& p, double r, double ps, 
     }
   }
   const double x3 = r - p.r03;
-  const double g = p.a * exp(-p.beta1 * x3 * x3);
+  const double g = p.a * exp_tab(-p.beta1 * x3 * x3, etab);
   // exp(-x) is +0 in double precision for x above 745.2; the refit's second density
   // term (beta2 = 535.661 /A, r04 = -261.984 A) is always there, so it is skipped
   const double xe = p.beta2 * (r - p.r04);
-  const double e = xe > 746.0 ? 0.0 : exp(-xe);
+  const double e = xe > 746.0 ? 0.0 : exp_tab(-xe, etab);
   rho = (g + e) * ps;
   drho = (-2.0 * p.beta1 * x3 * g - p.beta2 * e) * ps + (g + e) * dps;
 }
@@ -91,6 +91,8 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
                                                      double* __restrict__ ufp, double* __restrict__ u_out,
                                                      const double* __restrict__ wl, double* __restrict__ dufp,
                                                      double* __restrict__ du_out) {
+  __shared__ double etab[32];
+  stage_exp_table(etab);
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
@@ -115,15 +117,15 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
       const double dz = min_image(pz[u] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (k0 + u < cnt && r2 < p.rc2) {
-        const double r = sqrt(r2);
+        const double r = r2 * rsq_nr(r2);
         double ps, dps;
         taper((r - p.rc) * p.inv_h, ps, dps);
         if constexpr (KIND == APX_EAM_CLOSED) {
-          rho += exp(-p.beta * (r - p.r0)) * ps;
-          pair += exp(-p.alpha * (r - p.r0)) * ps;
+          rho += exp_tab(-p.beta * (r - p.r0), etab) * ps;
+          pair += exp_tab(-p.alpha * (r - p.r0), etab) * ps;
         } else {
           double phi, dphi, rr, drr;
-          eam2_pair(p, r, ps, dps * p.inv_h, phi, dphi, rr, drr);
+          eam2_pair(p, r, ps, dps * p.inv_h, phi, dphi, rr, drr, etab);
           rho += rr;
           pair += phi;
         }
@@ -159,6 +161,8 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
                                                    const int* __restrict__ count, const int* __restrict__ idx,
                                                    int max_nb, const double* __restrict__ ufp,
                                                    const double* __restrict__ u, double* __restrict__ f) {
+  __shared__ double etab[32];
+  stage_exp_table(etab);
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
@@ -187,22 +191,23 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (SKIPZERO && ui == 0.0 && uj[q] == 0.0) continue;
       if (k0 + q < cnt && r2 < p.rc2) {
-        const double r = sqrt(r2);
+        const double ir = rsq_nr(r2);
+        const double r = r2 * ir;
         double ps, dps;
         taper((r - p.rc) * p.inv_h, ps, dps);
         dps *= p.inv_h;
         double drho, dphi;
         if constexpr (KIND == APX_EAM_CLOSED) {
-          const double eb = exp(-p.beta * (r - p.r0));
-          const double ea = exp(-p.alpha * (r - p.r0));
+          const double eb = exp_tab(-p.beta * (r - p.r0), etab);
+          const double ea = exp_tab(-p.alpha * (r - p.r0), etab);
           drho = eb * (dps - p.beta * ps);
           dphi = p.A * ea * (dps - p.alpha * ps);
         } else {
           double phi, rr;
-          eam2_pair(p, r, ps, dps, phi, dphi, rr, drho);
+          eam2_pair(p, r, ps, dps, phi, dphi, rr, drho, etab);
         }
         const double s = 0.5 * (ui + uj[q]) * dphi + (ufi + fj[q]) * drho;
-        const double sr = s / r;
+        const double sr = s * ir;
         fx += sr * dx;
         fy += sr * dy;
         fz += sr * dz;

@@ -269,7 +269,7 @@ apx_status md_weights(apx_md* md, const double* pos, double* w) {
                           md->w0x.as<double>());
     if (s != APX_OK) return s;
     apx_prec_params p1 = md->prec;
-    p1.flags = APX_PREC_CSP_GIVEN;
+    p1.flags = md->prec.flags | APX_PREC_CSP_GIVEN;
     s = md_precision(md, nl, p1, md->w0x.as<double>(), w, &na);
     if (s != APX_OK) return s;
     md->n_active = na;

@@ -329,3 +329,34 @@ def test_verlet_matches_oracle(ops_ctx):
     assert np.array_equal(w.cpu().numpy() > 0, ref["w"] > 0)
     assert abs(st["e_pot"] - ref["e_pot"][-1]) < 1e-7
     assert st["precision_updates"] == 2
+
+
+def test_fp64_pair_functions_against_libm(ops_ctx):
+    """The FP64 exponential, reciprocal and reciprocal square root of the pair loops against
+    numpy (the host libm) on their argument ranges: exp within 4 ulp, 1/x and 1/sqrt(x)
+    within 2 ulp."""
+    ops, ctx = ops_ctx
+    _case("fp64 pair-loop functions")
+    rng = np.random.default_rng(31)
+    n = 1 << 20
+    xe = np.concatenate([rng.uniform(-40.0, 12.0, n), rng.uniform(-745.0, 709.0, 1024), [0.0, -1e-300, 1e-17]])
+    xr = np.concatenate([rng.uniform(0.5, 40.0, n), 10.0 ** rng.uniform(-30, 30, 4096)])
+    out = {}
+    for name, x in (("e", xe), ("r", xr)):
+        xd = torch.as_tensor(x, device="cuda")
+        e = torch.empty_like(xd)
+        rc = torch.empty_like(xd)
+        rs = torch.empty_like(xd)
+        ctx._check(ctx.lib.apx_fp64_functions(ctx.h, xd.numel(), xd.data_ptr(), e.data_ptr(), rc.data_ptr(),
+                                              rs.data_ptr()))
+        out[name] = (e.cpu().numpy(), rc.cpu().numpy(), rs.cpu().numpy())
+
+    def ulps(a, b):
+        return np.abs(a - b) / np.spacing(np.abs(b))
+
+    ref = np.exp(xe)
+    keep = ref > np.finfo(np.float64).tiny  # normal results
+    assert ulps(out["e"][0][keep], ref[keep]).max() <= 4.0
+    assert np.all(out["e"][0][~keep] <= 2 * np.finfo(np.float64).tiny)
+    assert ulps(out["r"][1], 1.0 / xr).max() <= 2.0
+    assert ulps(out["r"][2], 1.0 / np.sqrt(xr)).max() <= 2.0
