@@ -511,7 +511,11 @@ def main():
     stats = model.stats()
 
     def run(mode, steps, warm, profile, avg_samples=0, avg_dw_min=0.0, prec_set=None, ace_precision="fp32",
-            thermostat=None):
+            thermostat=None, prof_steps=None):
+        """Warm-up, then `steps` timed steps without profiling (the step loop then waits on
+        the device only for the rebuild test); with `profile`, `prof_steps` (default
+        `steps`) more steps of the same trajectory under the library's event timers give
+        the per-kernel and per-class times (st["prof"] holds their statistics)."""
         md = ops.MD(ctx, atoms, eam_p, model, prec_set or prec, dt=1e-3, skin=0.5, max_nb=80, precision_every=10,
                     ace_precision=ace_precision, mode=mode, indenter=ind, avg_samples=avg_samples,
                     avg_dw_min=avg_dw_min, thermostat=thermostat)
@@ -521,15 +525,21 @@ def main():
         if warm:
             md.step(pos, vel, f, w, warm)
         torch.cuda.synchronize()
-        if profile:
-            ctx.profile(True)
         t0 = time.perf_counter()
         st = md.step(pos, vel, f, w, steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        prof = ctx.profile_read() if profile else {}
-        ctx.profile(False)
-        tim = md.timings()
+        prof, tim = {}, [0.0] * 5
+        if profile:
+            ps = prof_steps or steps
+            ctx.profile(True)
+            st_p = md.step(pos, vel, f, w, ps)
+            torch.cuda.synchronize()
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            tim = [t * steps / ps for t in md.timings()]  # per `steps` steps, as class_times expects
+            st["prof"] = {"steps": ps, "ace_atoms": st_p["ace_atoms"], "thermo_corrected": st_p["thermo_corrected"],
+                          "thermo_steps": st_p["thermo_steps"]}
         md.close()
         return dt, st, prof, tim
 
@@ -557,7 +567,7 @@ def main():
         return
     # live per-kernel roofline of the adaptive timed region
     nb_avg = 60.0
-    n_act = st_a["ace_atoms"] / K
+    n_act = st_a["prof"]["ace_atoms"] / st_a["prof"]["steps"]
     # ACE work per launch: the mean number of atoms ACE was evaluated for over the timed
     # steps (the detected set changes at every weight update)
     models = kernel_models(stats, n, n_act, nb_avg, 42.0)
@@ -599,7 +609,7 @@ def main():
 
     if not args.no_fp64:
         log(f"adaptive with float64 ACE: {W} warm-up + {K} timed steps")
-        dt_d, st_d, _, tim_d = run("adaptive", K, W, False, ace_precision="fp64")
+        dt_d, st_d, _, tim_d = run("adaptive", K, W, True, ace_precision="fp64", prof_steps=10)
         result["fp64_ace"] = {"atom_steps_per_s": n * K / dt_d, "ms_per_step": dt_d / K * 1e3,
                               "active_atoms_mean": st_d["ace_atoms"] / K, "class_ms_per_step": class_times(tim_d, K)}
         log(f"float64 ACE {dt_d / K * 1e3:.3f} ms/step")
@@ -611,7 +621,8 @@ def main():
         na, wa = 11, 2 * 10 * 11 + 10
         log(f"time-averaged weights ({na} samples): {wa} warm-up + {K} timed steps")
         dt_t, st_t, prof_t, tim_t = run("adaptive", K, wa, True, avg_samples=na, avg_dw_min=1.0 / na)
-        models_t = kernel_models(stats, n, st_t["ace_atoms"] / K, nb_avg, 42.0, avg_samples=na)
+        models_t = kernel_models(stats, n, st_t["prof"]["ace_atoms"] / st_t["prof"]["steps"], nb_avg, 42.0,
+                                 avg_samples=na)
         result["time_averaged"] = {
             "avg_samples": na, "window_fs": 10 * na, "dw_min": 1.0 / na, "warmup": wa, "window": "past",
             "atom_steps_per_s": n * K / dt_t, "ms_per_step": dt_t / K * 1e3,
@@ -643,7 +654,7 @@ def main():
     if not args.no_hyb2:
         # the paper's Hyb2 set: spreading radii 8/20 A instead of 4/12 A
         log(f"Hyb2 weights: {W} warm-up + {K} timed steps")
-        dt_h, st_h, prof_h, tim_h = run("adaptive", K, W, False, prec_set=synth.precision_hyb2())
+        dt_h, st_h, prof_h, tim_h = run("adaptive", K, W, True, prec_set=synth.precision_hyb2(), prof_steps=10)
         result["hyb2"] = {"r_lo": 8.0, "r_hi": 20.0, "atom_steps_per_s": n * K / dt_h, "ms_per_step": dt_h / K * 1e3,
                           "active_atoms_mean": st_h["ace_atoms"] / K, "class_ms_per_step": class_times(tim_h, K)}
         log(f"Hyb2 {dt_h / K * 1e3:.3f} ms/step, active mean {st_h['ace_atoms'] / K:.0f}")
@@ -675,12 +686,12 @@ def main():
 
     if not args.no_full:
         log(f"full ACE: 1 warm-up + {KF} timed steps")
-        dt_f, st_f, prof_f, tim_f = run("full_ace", KF, 1, True)
+        dt_f, st_f, prof_f, tim_f = run("full_ace", KF, 1, True, prof_steps=min(KF, 10))
         full = n * KF / dt_f
         result["full_ace_atom_steps_per_s"] = full
         result["full_ace_ms_per_step"] = dt_f / KF * 1e3
         result["adaptive_over_full_ace"] = adaptive / full
-        n_f = st_f["ace_atoms"] / KF
+        n_f = st_f["prof"]["ace_atoms"] / st_f["prof"]["steps"]
         mf = kernel_models(stats, n, n_f, nb_avg, 42.0)
         for k in ("ace.energy", "ace.adjoint"):
             if k in prof_f:

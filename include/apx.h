@@ -397,7 +397,8 @@ typedef struct apx_mlp apx_mlp;
 apx_status apx_md_set_mlp(apx_md* md, apx_mlp* mlp, double tau_lo, double tau_hi);
 /* Device timers of the last apx_verlet_step call, milliseconds summed over its steps:
  * out[0] half kick + drift + neighbour rebuilds, [1] weight updates, [2] EAM, [3] ACE,
- * [4] blend + indenter + half kick. */
+ * [4] blend + indenter + half kick.  Collected only while profiling is on for the context
+ * (apx_profile_enable), which adds one device wait per step; zeros otherwise. */
 apx_status apx_md_timings(apx_md* md, double* out5);
 
 /* ------------------------------------------------ learned precision indicator */

@@ -107,10 +107,18 @@ __device__ __forceinline__ void solid_harmonics(T x, T y, T z, T* S, T* Sx, T* S
   }
 }
 
+// Reciprocal in the evaluation type: the hardware estimate (1 ulp) in float32, two Newton
+// steps on it in float64.
+template <class T>
+__device__ __forceinline__ T rcp_t(T a) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(a);
+  else return rcp_nr(a);
+}
+
 __device__ __forceinline__ void taper_d(double x, double& p, double& dp) {
   const double x2 = x * x;
   const double x4 = x2 * x2;
-  const double den = 1.0 / (1.0 + x4);
+  const double den = rcp_nr(1.0 + x4);
   p = x4 * den;
   dp = 4.0 * x2 * x * den * den;
 }
@@ -119,10 +127,26 @@ template <class T>
 __device__ __forceinline__ void taper_t(T x, T& p, T& dp) {
   const T x2 = x * x;
   const T x4 = x2 * x2;
-  const T den = T(1) / (T(1) + x4);
+  const T den = rcp_t<T>(T(1) + x4);
   p = x4 * den;
   dp = T(4) * x2 * x * den * den;
 }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// LDS layout of the atomic-base kernel: per neighbour slot (columns, row stride kStride)
+// the radial values g_k (12 rows) and solid harmonics S_lm (LM rows); A' reuses the space
+// once the contraction is done.  Float32 contracts on the matrix cores.
+template <class T, int LMAX>
+struct BasisLds {
+  static constexpr int LM = (LMAX + 1) * (LMAX + 1);
+  static constexpr bool kMfma = sizeof(T) == 4;
+  static constexpr int kStride = kMfma ? 66 : 65;
+  static constexpr int kGRows = 12;
+  static constexpr int kSRows = LM;
+  static constexpr size_t bytes() { return sizeof(T) * ((size_t)(kGRows + kSRows) * kStride); }
+  static_assert(12 * LM <= (kGRows + kSRows) * kStride, "A' fits in the neighbour tables");
+};
 
 // ------------------------------------------------------------------ kernel 1
 template <class T, int LMAX>
@@ -133,10 +157,14 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
                                                   AnchorDev an, AceScratch<T> sc) {
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
   constexpr int kMaxK = 12;
+  constexpr bool MF = BasisLds<T, LMAX>::kMfma;
+  constexpr int ST = BasisLds<T, LMAX>::kStride, GR = BasisLds<T, LMAX>::kGRows, SR = BasisLds<T, LMAX>::kSRows;
   extern __shared__ double smem_raw[];
-  T* gS = reinterpret_cast<T*>(smem_raw);  // [K][65]
-  T* sS = gS + kMaxK * 65;                 // [LM][65]
-  T* Ap = sS + LM * 65;                    // [K*LM]
+  T* gS = reinterpret_cast<T*>(smem_raw);  // [GR][ST]: g_k per neighbour slot
+  T* sS = gS + GR * ST;                    // [SR][ST]: S_lm per neighbour slot
+  T* Ap = gS;                              // [K*LM], after the contraction
+  __shared__ double etab[32];
+  stage_exp_table(etab);
   const int q = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   const int i = active[q];
@@ -147,11 +175,14 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
   T acc[5];
 #pragma unroll
   for (int s = 0; s < 5; ++s) acc[s] = T(0);
+  floatx4 D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
   double rho_a = 0.0, pair_a = 0.0;
+  const T two_rc = T(2) / rc;
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const int k = c0 + lane;
     T g[kMaxK];
     T S[LM];
+    bool inside = false;
 #pragma unroll
     for (int a = 0; a < kMaxK; ++a) g[a] = T(0);
 #pragma unroll
@@ -162,11 +193,13 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
       const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
       const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rc2) {
-        const double rd = sqrt(r2);
+      const double ird = rsq_nr(r2);
+      const double rd = r2 * ird;
+      inside = r2 < rc2;
+      if (inside) {
         const T r = T(rd);
-        const T ir = T(1.0 / rd);
-        const T x = T(2) * r / rc - T(1);
+        const T ir = T(ird);
+        const T x = r * two_rc - T(1);
         T ps, dps;
         taper_t<T>((r - rc) * inv_h, ps, dps);
         T t0 = T(1), t1 = x;
@@ -182,36 +215,74 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
         solid_harmonics<T, LMAX, false>(T(dx) * ir, T(dy) * ir, T(dz) * ir, S, nullptr, nullptr, nullptr);
       }
       if (an.on && r2 < an.rc2) {
-        const double r = sqrt(r2);
         double ps, dps;
-        taper_d((r - an.rc) * an.inv_h, ps, dps);
-        rho_a += exp(-an.beta * (r - an.r0)) * ps;
-        pair_a += exp(-an.alpha * (r - an.r0)) * ps;
+        taper_d((rd - an.rc) * an.inv_h, ps, dps);
+        rho_a += exp_tab(-an.beta * (rd - an.r0), etab) * ps;
+        pair_a += exp_tab(-an.alpha * (rd - an.r0), etab) * ps;
       }
+    }
+    // neighbour slot of the lane: float32 compacts the neighbours inside the cutoff to the
+    // front (the others, all zero, follow), so that the matrix steps stop after them
+    int slot = lane, steps = 0;
+    if constexpr (MF) {
+      const unsigned long long m = __ballot(inside);
+      const int nv = __popcll(m);
+      const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      slot = inside ? below : nv + (lane - below);
+      steps = (nv + 3) >> 2;
     }
 #pragma unroll
     for (int a = 0; a < kMaxK; ++a)
-      if (a < K) gS[a * 65 + lane] = g[a];
+      if (a < K) gS[a * ST + slot] = g[a];
 #pragma unroll
-    for (int a = 0; a < LM; ++a) sS[a * 65 + lane] = S[a];
+    for (int a = 0; a < LM; ++a) sS[a * ST + slot] = S[a];
     __syncthreads();
-    const int lim = (cnt - c0) < 64 ? (cnt - c0) : 64;
+    if constexpr (MF) {
+      // A'[k][lm] += sum over 4 slots per step of g[k][slot] S[lm][slot] on the matrix
+      // cores (16 x 16 x 4 float32): lane = row/column (lane % 16) and slot in the step
+      // (lane / 16), operand rows beyond K and LM are zero; the row stride of 66 keeps
+      // the two lane halves on distinct banks
+      const int col = lane & 15, sub = lane >> 4;
+      const bool g_row = col < K, s_row = 16 + col < LM;
+      for (int st = 0; st < steps; ++st) {
+        const int sl = 4 * st + sub;
+        const float av = g_row ? gS[col * ST + sl] : 0.f;
+        D0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sS[col * ST + sl], D0, 0, 0, 0);
+        if constexpr (LM > 16)
+          D1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_row ? sS[(16 + col) * ST + sl] : 0.f, D1, 0, 0, 0);
+      }
+    } else {
+      const int lim = (cnt - c0) < 64 ? (cnt - c0) : 64;
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      const int o = lane + 64 * s;
-      if (o < nout) {
-        const int kk = o / LM, lm = o - kk * LM;
-        T v = acc[s];
-        for (int nb = 0; nb < lim; ++nb) v += gS[kk * 65 + nb] * sS[lm * 65 + nb];
-        acc[s] = v;
+      for (int s = 0; s < 5; ++s) {
+        const int o = lane + 64 * s;
+        if (o < nout) {
+          const int kk = o / LM, lm = o - kk * LM;
+          T v = acc[s];
+          for (int nb = 0; nb < lim; ++nb) v += gS[kk * ST + nb] * sS[lm * ST + nb];
+          acc[s] = v;
+        }
       }
     }
     __syncthreads();
   }
+  if constexpr (MF) {
+    // accumulator layout: row k = 4 (lane / 16) + r, column lane % 16 (+ 16 for D1)
+    const int col = lane & 15, sub = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
-    const int o = lane + 64 * s;
-    if (o < nout) Ap[o] = acc[s];
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * sub + r;
+      if (k < K) {
+        Ap[k * LM + col] = D0[r];
+        if (16 + col < LM) Ap[k * LM + 16 + col] = D1[r];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const int o = lane + 64 * s;
+      if (o < nout) Ap[o] = acc[s];
+    }
   }
   __syncthreads();
   const int na = K * LM;
@@ -331,19 +402,29 @@ __device__ __forceinline__ void pair_fwd_deg(const T* __restrict__ As, const int
     if (q0 < q1) {
       const int n30 = __builtin_amdgcn_readfirstlane((rec[10 + L] - L * L) / P2);
       const int n3e = n30 + (q1 - q0);
+      // the coefficients of n3 = 0 .. NMAX-1 around the run, read at once (scalar loads
+      // from a uniform base; the table is padded on both sides), and the run as a bit mask
+      static_assert(NMAX <= kTcPad, "the coefficient table is padded by kTcPad entries");
+      const Coef2<T>* cb = tb.tc + (q0 - n30);
+      T c1v[NMAX], c2v[NMAX];
+#pragma unroll
+      for (int n3 = 0; n3 < NMAX; ++n3) {
+        c1v[n3] = cld(&cb[n3].c1);
+        c2v[n3] = cld(&cb[n3].c2);
+      }
+      const unsigned run = ((1u << n3e) - 1u) & ~((1u << n30) - 1u);
       T P[2 * L + 1];
 #pragma unroll
       for (int m = 0; m < 2 * L + 1; ++m) P[m] = T(0);
       Couple3<LMAX, L1, L2, L>::template fwd<T>(a, bb, P);
 #pragma unroll
       for (int n3 = 0; n3 < NMAX; ++n3) {
-        if (n3 >= n30 && n3 < n3e) {
-          const Coef2<T>* c = tb.tc + (q0 + n3 - n30);
+        if (run & (1u << n3)) {
           T B = T(0);
 #pragma unroll
           for (int mm = 0; mm < 2 * L + 1; ++mm) B = fma(P[mm], As[(n3 * P2 + L * L + mm) * ST + t], B);
-          p1 = fma(cld(&c->c1), B, p1);
-          p2 = fma(cld(&c->c2), B, p2);
+          p1 = fma(c1v[n3], B, p1);
+          p2 = fma(c2v[n3], B, p2);
         }
       }
     }
@@ -645,7 +726,14 @@ __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ A
 }
 
 // ------------------------------------------------------------------ kernel 3
-template <class T, int LMAX>
+// Ā' of one atom in LDS: lm-major rows of KP radial values (K rounded up to whole 16-byte
+// groups, the padding zero), so that a row is read by a few wide broadcast loads.
+template <class T, int NMAX>
+struct ForceLds {
+  static constexpr int KP = (NMAX * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
+};
+
+template <class T, int LMAX, int NMAX>
 __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos, int n, BoxDev b,
                                                   const int* __restrict__ count, const int* __restrict__ idx,
                                                   int max_nb, const int* __restrict__ active, int n_act, int K,
@@ -654,10 +742,14 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
                                                   double* __restrict__ f, const double* __restrict__ w2,
                                                   double* __restrict__ f2) {
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
-  constexpr int kMaxK = 12;
+  constexpr int kMaxK = NMAX;
+  constexpr int KP = ForceLds<T, NMAX>::KP;
   extern __shared__ double smem_raw[];
-  T* Ab2 = reinterpret_cast<T*>(smem_raw);  // [K][LM]
+  T* Ab2 = reinterpret_cast<T*>(smem_raw);  // [LM][KP]: Ab2[lm * KP + k], zero for k >= K
+  __shared__ double etab[32];
+  stage_exp_table(etab);
   const int q = xcd_block(blockIdx.x, gridDim.x);
+  const T two_rc = T(2) / rc;
   const int lane = threadIdx.x;
   const int i = active[q];
   const double wi = w ? w[i] : 1.0;
@@ -669,9 +761,14 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
   const int as = ts > 0 ? ts : 1;
   // back-projection: Ab2[k][lm] = sum_n Wp[l][n][k] Abar[n][lm]; the float32 unit path
   // has it precomputed tile-major in sc.A by k_ace_backproject
+  for (int o = lane; o < LM * KP; o += 64) Ab2[o] = T(0);
+  __syncthreads();
   if (ts > 0) {
     const T* B = sc.A + (size_t)(q / ts) * na * ts + (q % ts);
-    for (int o = lane; o < K * LM; o += 64) Ab2[o] = B[(size_t)o * ts];
+    for (int o = lane; o < K * LM; o += 64) {
+      const int kk = o / LM, lm = o - kk * LM;
+      Ab2[lm * KP + kk] = B[(size_t)o * ts];
+    }
   }
   for (int o = lane; o < K * LM && ts == 0; o += 64) {
     const int kk = o / LM, lm = o - kk * LM;
@@ -687,7 +784,7 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
     T v = T(0);
 #pragma unroll
     for (int nn = 0; nn < kMaxK; ++nn) v += wv_[nn] * av_[nn];
-    Ab2[o] = v;
+    Ab2[lm * KP + kk] = v;
   }
   __syncthreads();
   const double fpa = an.on ? sc.fp_anch[q] : 0.0;
@@ -705,12 +802,13 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
       const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       double gx = 0.0, gy = 0.0, gz = 0.0;
+      const double ird = rsq_nr(r2);
+      const double rd = r2 * ird;
       if (r2 < rc2) {
-        const double rd = sqrt(r2);
-        const T r = T(rd), ir = T(1.0 / rd);
+        const T r = T(rd), ir = T(ird);
         const T ux = T(dx) * ir, uy = T(dy) * ir, uz = T(dz) * ir;
-        const T x = T(2) * r / rc - T(1);
-        const T dxdr = T(2) / rc;
+        const T dxdr = two_rc;
+        const T x = r * dxdr - T(1);
         T ps, dps;
         taper_t<T>((r - rc) * inv_h, ps, dps);
         dps *= inv_h;
@@ -738,11 +836,27 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
         for (int lm = 0; lm < LM; ++lm) {
           int l = 0;
           while ((l + 1) * (l + 1) <= lm) ++l;
+          // the row is the same for every lane (broadcast); entries beyond K are zero
+          T c[KP];
+#pragma unroll
+          for (int kk = 0; kk < KP; kk += 16 / (int)sizeof(T)) {
+            if constexpr (sizeof(T) == 4) {
+              const float4 v = *reinterpret_cast<const float4*>(&Ab2[lm * KP + kk]);
+              c[kk] = v.x;
+              c[kk + 1] = v.y;
+              c[kk + 2] = v.z;
+              c[kk + 3] = v.w;
+            } else {
+              const double2 v = *reinterpret_cast<const double2*>(&Ab2[lm * KP + kk]);
+              c[kk] = v.x;
+              c[kk + 1] = v.y;
+            }
+          }
           T av = T(0), bv = T(0);
-          for (int kk = 0; kk < K; ++kk) {
-            const T c = Ab2[kk * LM + lm];
-            av = fma(c, g[kk], av);
-            bv = fma(c, gd[kk], bv);
+#pragma unroll
+          for (int kk = 0; kk < NMAX; ++kk) {
+            av = fma(c[kk], g[kk], av);
+            bv = fma(c[kk], gd[kk], bv);
           }
           radial += (bv - av * T(l) * ir) * S[lm];
           const T ar = av * ir;
@@ -755,15 +869,14 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
         gz = (double)(radial * uz + vz);
       }
       if (an.on && r2 < an.rc2) {
-        const double r = sqrt(r2);
         double ps, dps;
-        taper_d((r - an.rc) * an.inv_h, ps, dps);
+        taper_d((rd - an.rc) * an.inv_h, ps, dps);
         dps *= an.inv_h;
-        const double eb = exp(-an.beta * (r - an.r0));
-        const double ea = exp(-an.alpha * (r - an.r0));
+        const double eb = exp_tab(-an.beta * (rd - an.r0), etab);
+        const double ea = exp_tab(-an.alpha * (rd - an.r0), etab);
         const double drho = eb * (dps - an.beta * ps);
         const double dphi = an.A * ea * (dps - an.alpha * ps);
-        const double s = (fpa * drho + 0.5 * dphi) / r;
+        const double s = (fpa * drho + 0.5 * dphi) * ird;
         gx += s * dx;
         gy += s * dy;
         gz += s * dz;
@@ -1249,7 +1362,7 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
   }
   const T rc = (T)m->r_cut, inv_h = (T)(1.0 / m->h);
   const double rc2 = m->r_cut * m->r_cut;
-  const size_t lds1 = sizeof(T) * (12 * 65 + LM * 65 + 12 * LM);
+  const size_t lds1 = BasisLds<T, LMAX>::bytes();
   {
   ProfScope ps(ctx, "ace.basis");
   k_ace_basis<T, LMAX><<<n_act, 64, lds1, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
@@ -1367,11 +1480,17 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
     k_ace_backproject<T, LMAX><<<(unsigned)(n_pad / TILE), 256, 0, ctx->stream>>>(sc.Ab, sc.A, tb.Wp, m->n_max, na);
     APX_LAUNCH_CHECK(ctx);
   }
-  const size_t lds3 = sizeof(T) * (size_t)m->n_max * LM;
   ProfScope ps(ctx, "ace.force");
-  k_ace_force<T, LMAX><<<n_act, 64, lds3, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb, active,
-                                                         n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an, sc, w, f, w2,
-                                                         f2);
+  auto force = [&](auto nmax_c) {
+    constexpr int NM = decltype(nmax_c)::value;
+    const size_t lds3 = sizeof(T) * (size_t)ForceLds<T, NM>::KP * LM;
+    k_ace_force<T, LMAX, NM><<<n_act, 64, lds3, ctx->stream>>>(atoms->pos, n, b, nl->count, nl->idx, nl->max_nb,
+                                                               active, n_act, m->n_max, rc, inv_h, rc2, tb.Wp, an,
+                                                               sc, w, f, w2, f2);
+  };
+  if (m->n_max <= 8) force(std::integral_constant<int, 8>{});
+  else if (m->n_max <= 10) force(std::integral_constant<int, 10>{});
+  else force(std::integral_constant<int, 12>{});
   APX_LAUNCH_CHECK(ctx);
   return APX_OK;
 }

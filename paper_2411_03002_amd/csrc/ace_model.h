@@ -46,12 +46,14 @@ struct alignas(2 * sizeof(T)) Coef2 {
 };
 
 // Pointers into one precision's copy of the tables.
+constexpr int kTcPad = 12;  // zero coefficient pairs around the triple table (>= the largest n_max)
+
 template <class T>
 struct AceTables {
   const T* Wp;        // [l_max+1][n_max][n_max], W[l][n][k] * N_l / s_a
   const int* pairs;   // [npairs][kPairRec], sorted by type
   const int* t_v;     // [ntrip] basis index
-  const Coef2<T>* tc; // [ntrip + 1] (c1, c2) per triple, one padding entry
+  const Coef2<T>* tc; // [ntrip] (c1, c2) per triple, kTcPad zero entries before and after
   const int* b1_off;  // [nb1]
   const int* b1_v;
   const T* b1_c1;

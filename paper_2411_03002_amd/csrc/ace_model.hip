@@ -316,13 +316,15 @@ static void fill_reals(std::vector<T>& out, const apx_ace_model* m, const Catalo
       for (int k = 0; k < nm; ++k) out.push_back((T)(m->W[((size_t)l * nm + n) * nm + k] * nl / m->s_a));
   }
   while (out.size() % 4) out.push_back((T)0);
+  // the triples' coefficients with kTcPad zero pairs on either side: a kernel reads the
+  // n_max coefficients around a run at once, whatever part of them the run uses
+  for (int k = 0; k < 2 * kTcPad; ++k) out.push_back((T)0);
   offs[1] = out.size();
   for (int v : c.t_v) {
     out.push_back((T)c1[v]);
     out.push_back((T)c2[v]);
   }
-  out.push_back((T)0);
-  out.push_back((T)0);
+  for (int k = 0; k < 2 * kTcPad; ++k) out.push_back((T)0);
   offs[2] = out.size();
   offs[3] = out.size();
   for (int v : c.b1_v) out.push_back((T)c1[v]);

@@ -22,7 +22,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // Minimum image of d = x_j - x_i along one axis of length L (both coordinates in
-// [lo, hi)): d -= L if d >= L/2; d += L if d < -L/2.
+// [lo, hi)): d -= L if d >= L/2; d += L if d < -L/2.  (Written as branches: few pairs
+// wrap, and a branch no lane takes costs less than forming both shifted values.)
 __device__ __forceinline__ double min_image(double d, double L, double half, int periodic) {
   if (periodic) {
     if (d >= half) d -= L;
@@ -99,6 +100,16 @@ __device__ __forceinline__ double rsq_nr(double a) {
 __device__ __forceinline__ void stage_exp_table(double* sh) {
   if (threadIdx.x < 32) sh[threadIdx.x] = kExp2Table[threadIdx.x];
   __syncthreads();
+}
+
+// atomicMax on a single global word that many waves update: a device-scope load (from L2,
+// not a stale L1 line) first, and the atomic only when v exceeds the value seen.  Atomics
+// to one address serialise in one L2 channel; most callers find the maximum already set.
+__device__ __forceinline__ void sparse_atomic_max(int* p, int v) {
+  if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+__device__ __forceinline__ void sparse_atomic_max(unsigned long long* p, unsigned long long v) {
+  if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
 }
 
 template <class T>

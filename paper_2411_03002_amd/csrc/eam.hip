@@ -88,9 +88,8 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
                                                      const int* __restrict__ count, const int* __restrict__ idx,
                                                      int max_nb, const double* __restrict__ w,
                                                      double* __restrict__ e_site, double* __restrict__ rho_out,
-                                                     double* __restrict__ ufp, double* __restrict__ u_out,
-                                                     const double* __restrict__ wl, double* __restrict__ dufp,
-                                                     double* __restrict__ du_out) {
+                                                     double2* __restrict__ uf, const double* __restrict__ wl,
+                                                     double2* __restrict__ duf) {
   __shared__ double etab[32];
   stage_exp_table(etab);
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -144,13 +143,11 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
   }
   if (rho_out) rho_out[i] = rho;
   const double u = w ? 1.0 - w[i] : 1.0;
-  ufp[i] = u * Fp;
-  u_out[i] = u;
-  if (dufp) {
+  uf[i] = make_double2(u, u * Fp);
+  if (duf) {
     // weights of a second set wl: the EAM weight difference (1 - wl) - (1 - w) = w - wl
     const double du = w[i] - wl[i];
-    dufp[i] = du * Fp;
-    du_out[i] = du;
+    duf[i] = make_double2(du, du * Fp);
   }
 }
 
@@ -159,14 +156,15 @@ __global__ void __launch_bounds__(256) k_eam_density(const double* __restrict__ 
 template <int KIND, bool SKIPZERO = false>
 __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ pos, int n, BoxDev b, EamDev p,
                                                    const int* __restrict__ count, const int* __restrict__ idx,
-                                                   int max_nb, const double* __restrict__ ufp,
-                                                   const double* __restrict__ u, double* __restrict__ f) {
+                                                   int max_nb, const double2* __restrict__ uf,
+                                                   double* __restrict__ f) {
   __shared__ double etab[32];
   stage_exp_table(etab);
   const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[(size_t)n + i], zi = pos[2 * (size_t)n + i];
-  const double ui = u[i], ufi = ufp[i];
+  const double2 ufs = uf[i];
+  const double ui = ufs.x, ufi = ufs.y;
   int cnt = count[i];
   if (cnt > max_nb) cnt = max_nb;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -180,8 +178,9 @@ __global__ void __launch_bounds__(256) k_eam_force(const double* __restrict__ po
       px[q] = pos[jb[q]];
       py[q] = pos[(size_t)n + jb[q]];
       pz[q] = pos[2 * (size_t)n + jb[q]];
-      uj[q] = u[jb[q]];
-      fj[q] = ufp[jb[q]];
+      const double2 v = uf[jb[q]];
+      uj[q] = v.x;
+      fj[q] = v.y;
     }
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
@@ -251,45 +250,44 @@ EamDev eam_dev(const apx_eam_params* p) {
   return d;
 }
 
-// Launches both passes; ufp/u are caller-provided scratch of n doubles each.  With wl and
-// df (and dufp/du, n doubles each), a second force pass writes df = the fast-potential
+// Launches both passes; uf is caller-provided scratch of 2n doubles (per atom u and u F').
+// With wl and df (and duf, 2n doubles), a second force pass writes df = the fast-potential
 // force with weights wl minus the one with weights w.
 apx_status eam_launch(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, const apx_eam_params* p,
-                      const double* w, double* e_site, double* rho, double* f, double* ufp, double* u,
-                      const double* wl = nullptr, double* df = nullptr, double* dufp = nullptr,
-                      double* du = nullptr) {
+                      const double* w, double* e_site, double* rho, double* f, double* uf,
+                      const double* wl = nullptr, double* df = nullptr, double* duf = nullptr) {
   const int n = (int)atoms->n;
   if (n == 0) return APX_OK;
   BoxDev b = make_box(atoms);
   EamDev d = eam_dev(p);
+  double2* uf2 = reinterpret_cast<double2*>(uf);
+  double2* duf2 = reinterpret_cast<double2*>(duf);
   {
   ProfScope ps(ctx, "eam.density");
   if (p->kind == APX_EAM2)
     k_eam_density<APX_EAM2><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx,
-                                                                         nl->max_nb, w, e_site, rho, ufp, u, wl,
-                                                                         dufp, du);
+                                                                         nl->max_nb, w, e_site, rho, uf2, wl, duf2);
   else
-    k_eam_density<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
-                                                                               nl->idx, nl->max_nb, w, e_site, rho,
-                                                                               ufp, u, wl, dufp, du);
+    k_eam_density<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+        atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb, w, e_site, rho, uf2, wl, duf2);
   APX_LAUNCH_CHECK(ctx);
   }
   ProfScope ps(ctx, "eam.force");
   if (p->kind == APX_EAM2)
     k_eam_force<APX_EAM2><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count, nl->idx,
-                                                                       nl->max_nb, ufp, u, f);
+                                                                       nl->max_nb, uf2, f);
   else
     k_eam_force<APX_EAM_CLOSED><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
-                                                                             nl->idx, nl->max_nb, ufp, u, f);
+                                                                             nl->idx, nl->max_nb, uf2, f);
   APX_LAUNCH_CHECK(ctx);
   if (df) {
     ProfScope pd(ctx, "eam.force_delta");
     if (p->kind == APX_EAM2)
       k_eam_force<APX_EAM2, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(atoms->pos, n, b, d, nl->count,
-                                                                               nl->idx, nl->max_nb, dufp, du, df);
+                                                                               nl->idx, nl->max_nb, duf2, df);
     else
       k_eam_force<APX_EAM_CLOSED, true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-          atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb, dufp, du, df);
+          atoms->pos, n, b, d, nl->count, nl->idx, nl->max_nb, duf2, df);
     APX_LAUNCH_CHECK(ctx);
   }
   return APX_OK;
@@ -302,8 +300,7 @@ apx_status eam_forces_dual(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist
   if (s != APX_OK) return s;
   if (!w || !wl || !df || !scratch4) return fail(ctx, APX_EINVAL, "dual EAM pass needs both weight sets");
   const size_t n = (size_t)atoms->n;
-  return eam_launch(ctx, atoms, nl, p, w, e_site, rho, f, scratch4, scratch4 + n, wl, df, scratch4 + 2 * n,
-                    scratch4 + 3 * n);
+  return eam_launch(ctx, atoms, nl, p, w, e_site, rho, f, scratch4, wl, df, scratch4 + 2 * n);
 }
 
 }  // namespace apx
@@ -319,6 +316,5 @@ extern "C" apx_status apx_eam_forces(apx_ctx* ctx, const apx_atoms* atoms, const
   const int n = (int)atoms->n;
   if (n > 0 && (!e_site || !f)) return fail(ctx, APX_EINVAL, "e_site and f are required");
   APX_ALLOC(ctx, ctx->dtmp, sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
-  double* ufp = ctx->dtmp.as<double>();
-  return eam_launch(ctx, atoms, nl, p, w, e_site, rho, f, ufp, ufp + n);
+  return eam_launch(ctx, atoms, nl, p, w, e_site, rho, f, ctx->dtmp.as<double>());
 }

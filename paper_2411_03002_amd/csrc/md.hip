@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(long long n, double* __restr
   if (threadIdx.x == 0) {
     double m = sh[0];
     for (int k = 1; k < 4; ++k) m = sh[k] > m ? sh[k] : m;
-    if (m > 0.0) atomicMax(maxd2, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0) sparse_atomic_max(maxd2, (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -521,8 +521,11 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
   BoxDev b = make_box(&md->atoms);
   apx_md_stats st{};
   for (int k = 0; k < 5; ++k) md->t_acc[k] = 0.0;
+  // class timers only while the context profiles: otherwise the step loop waits on the
+  // device once per step, for the rebuild test
+  const bool timed = ctx->prof;
   for (int64_t it = 0; it < n_steps; ++it) {
-    APX_HIP(ctx, hipEventRecord(md->ev[0], ctx->stream));
+    if (timed) APX_HIP(ctx, hipEventRecord(md->ev[0], ctx->stream));
     k_fill_d<<<1, 64, 0, ctx->stream>>>(1, scal + 3, 0.0);
     {
     ProfScope ps(ctx, "md.kick_drift");
@@ -542,7 +545,7 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
       if (s != APX_OK) return s;
       ++st.rebuilds;
     }
-    APX_HIP(ctx, hipEventRecord(md->ev[1], ctx->stream));
+    if (timed) APX_HIP(ctx, hipEventRecord(md->ev[1], ctx->stream));
     md->step += 1;
     const bool due = md->p.mode == APX_MODE_ADAPTIVE && md->p.precision_every > 0 &&
                      md->step % md->p.precision_every == 0;
@@ -554,7 +557,7 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
       md->w_dirty = true;
     }
     const bool dual = md->p.thermostat && md->w_dirty;
-    apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, true, dual, vel);
+    apx_status s = md_forces(md, pos, w, f, md->step * md->p.dt, timed, dual, vel);
     if (s != APX_OK) return s;
     st.ace_atoms += md->ace_count;
     {
@@ -584,7 +587,6 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
     }
     if (radicand) {
       // a skipped correction: the step is complete; report it before taking the next one
-      APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
       ++st.steps;
       if (stats) {
         s = md_stats(md, vel, st, stats);
@@ -593,15 +595,17 @@ extern "C" apx_status apx_verlet_step(apx_md* md, double* pos, double* vel, doub
       return fail(ctx, APX_ERADICAND, "thermostat: %lld corrections at step %lld had a negative radicand",
                   (long long)st.thermo_failed, md->step);
     }
-    APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
-    APX_HIP(ctx, hipEventSynchronize(md->ev[5]));
-    float ms = 0.f;
-    // ev0..ev1: integrate + rebuild, ev1..ev2: precision, ev2..ev3: EAM, ev3..ev4: ACE, ev4..ev5: blend+kick
-    if (hipEventElapsedTime(&ms, md->ev[0], md->ev[1]) == hipSuccess) md->t_acc[0] += ms;
-    if (hipEventElapsedTime(&ms, md->ev[1], md->ev[2]) == hipSuccess) md->t_acc[1] += ms;
-    if (hipEventElapsedTime(&ms, md->ev[2], md->ev[3]) == hipSuccess) md->t_acc[2] += ms;
-    if (hipEventElapsedTime(&ms, md->ev[3], md->ev[4]) == hipSuccess) md->t_acc[3] += ms;
-    if (hipEventElapsedTime(&ms, md->ev[4], md->ev[5]) == hipSuccess) md->t_acc[4] += ms;
+    if (timed) {
+      APX_HIP(ctx, hipEventRecord(md->ev[5], ctx->stream));
+      APX_HIP(ctx, hipEventSynchronize(md->ev[5]));
+      float ms = 0.f;
+      // ev0..ev1: integrate + rebuild, ev1..ev2: precision, ev2..ev3: EAM, ev3..ev4: ACE, ev4..ev5: blend+kick
+      if (hipEventElapsedTime(&ms, md->ev[0], md->ev[1]) == hipSuccess) md->t_acc[0] += ms;
+      if (hipEventElapsedTime(&ms, md->ev[1], md->ev[2]) == hipSuccess) md->t_acc[1] += ms;
+      if (hipEventElapsedTime(&ms, md->ev[2], md->ev[3]) == hipSuccess) md->t_acc[2] += ms;
+      if (hipEventElapsedTime(&ms, md->ev[3], md->ev[4]) == hipSuccess) md->t_acc[3] += ms;
+      if (hipEventElapsedTime(&ms, md->ev[4], md->ev[5]) == hipSuccess) md->t_acc[4] += ms;
+    }
     ++st.steps;
   }
   if (stats) {

@@ -179,39 +179,99 @@ struct ThermoArgs {
   int* counters;          // [0] corrected, [1] failed, [2] candidate overflow
 };
 
-// Visits the candidates of atom i (mobile j != i, r_ij^2 < r_omega^2) in the stencil cells
-// first_q, first_q + stride_q, ...; fn(j).
-template <class Fn>
-__device__ __forceinline__ void for_candidates(const ThermoArgs& A, const SearchGrid& g, int i, double xi, double yi,
-                                               double zi, int first_q, int stride_q, Fn&& fn) {
-  const int ci0 = (int)floor((xi - g.lo[0]) * g.inv[0]), ci1 = (int)floor((yi - g.lo[1]) * g.inv[1]),
-            ci2 = (int)floor((zi - g.lo[2]) * g.inv[2]);
+constexpr int kStCap = 1344;  // stencil cells of one atom (at most 11 per axis)
+
+// The search-grid stencil of the atom at (xi, yi, zi): for stencil cell q < total, the
+// first slot of its atoms in the cell list (st_base) and the exclusive prefix of the
+// stencil's cell sizes (st_pref[q], st_pref[total] = number of slots).  Cells outside a
+// non-periodic grid are empty.  Returns the number of slots; every thread calls it.
+__device__ int stencil_slots(const ThermoArgs& A, const SearchGrid& g, double xi, double yi, double zi,
+                             int* st_base, int* st_pref, int* shi) {
+  const int base[3] = {(int)floor((xi - g.lo[0]) * g.inv[0]), (int)floor((yi - g.lo[1]) * g.inv[1]),
+                       (int)floor((zi - g.lo[2]) * g.inv[2])};
   const int total = g.span[0] * g.span[1] * g.span[2];
-  for (int q = first_q; q < total; q += stride_q) {
-    int cc[3] = {q % g.span[0], (q / g.span[0]) % g.span[1], q / (g.span[0] * g.span[1])};
-    const int base[3] = {ci0, ci1, ci2};
-    bool skip = false;
-    int cell[3];
+  int carry = 0;
+  for (int q0 = 0; q0 < total; q0 += kThThreads) {
+    const int q = q0 + (int)threadIdx.x;
+    int size = 0;
+    if (q < total) {
+      const int cc[3] = {q % g.span[0], (q / g.span[0]) % g.span[1], q / (g.span[0] * g.span[1])};
+      bool skip = false;
+      int cell[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int b = base[d] < 0 ? 0 : (base[d] >= g.nc[d] ? g.nc[d] - 1 : base[d]);
-      int c = b + cc[d] + g.reach[d];
-      if (g.per[d]) c = ((c % g.nc[d]) + g.nc[d]) % g.nc[d];
-      else if (c < 0 || c >= g.nc[d]) skip = true;
-      cell[d] = c;
+      for (int d = 0; d < 3; ++d) {
+        const int b = base[d] < 0 ? 0 : (base[d] >= g.nc[d] ? g.nc[d] - 1 : base[d]);
+        int c = b + cc[d] + g.reach[d];
+        if (g.per[d]) c = ((c % g.nc[d]) + g.nc[d]) % g.nc[d];
+        else if (c < 0 || c >= g.nc[d]) skip = true;
+        cell[d] = c;
+      }
+      int first = 0;
+      if (!skip) {
+        const int c = cell[0] + g.nc[0] * (cell[1] + g.nc[1] * cell[2]);
+        first = A.cell_start[c];
+        size = A.cell_start[c + 1] - first;
+      }
+      st_base[q] = first;
     }
-    if (skip) continue;
-    const int c = cell[0] + g.nc[0] * (cell[1] + g.nc[1] * cell[2]);
-    for (int a = A.cell_start[c]; a < A.cell_start[c + 1]; ++a) {
-      const int j = A.cell_atoms[a];
-      if (j == i || (A.frozen && A.frozen[j])) continue;
-      const double dx = min_image(A.pos[j] - xi, g.L[0], g.half[0], g.per[0]);
-      const double dy = min_image(A.pos[(size_t)A.n + j] - yi, g.L[1], g.half[1], g.per[1]);
-      const double dz = min_image(A.pos[2 * (size_t)A.n + j] - zi, g.L[2], g.half[2], g.per[2]);
-      const double r2 = sq_dist_exact(dx, dy, dz);
-      if (r2 < A.r2om) fn(j);
+    int tot = 0;
+    const int ex = block_exclusive(size, shi, &tot);
+    if (q < total) st_pref[q] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) st_pref[total] = carry;
+  __syncthreads();
+  return carry;
+}
+
+// The candidates of atom i (mobile j != i with r_ij^2 < r_omega^2) in slot order: every
+// thread tests a contiguous range of slots (four loads in flight at a time) and marks
+// them in ctmp (the atom index, or -1); returns the thread's count.
+__device__ int mark_candidates(const ThermoArgs& A, const SearchGrid& g, int i, double xi, double yi, double zi,
+                               const int* st_base, const int* st_pref, int total, int M, int* ctmp) {
+  const int per = (M + kThThreads - 1) / kThThreads;
+  const int e0 = (int)threadIdx.x * per, e1 = e0 + per < M ? e0 + per : M;
+  if (e0 >= e1) return 0;
+  // stencil cell of the first slot: the last q with st_pref[q] <= e0
+  int lo = 0, hi = total - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st_pref[mid] <= e0) lo = mid;
+    else hi = mid - 1;
+  }
+  int q = lo, mine = 0;
+  for (int e = e0; e < e1; e += 4) {
+    int j[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = -1;
+      if (e + u < e1) {
+        while (st_pref[q + 1] <= e + u) ++q;
+        j[u] = A.cell_atoms[st_base[q] + (e + u - st_pref[q])];
+      }
+    }
+    double px[4], py[4], pz[4];
+    bool mob[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int jj = j[u] < 0 ? i : j[u];
+      px[u] = A.pos[jj];
+      py[u] = A.pos[(size_t)A.n + jj];
+      pz[u] = A.pos[2 * (size_t)A.n + jj];
+      mob[u] = !(A.frozen && A.frozen[jj]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (e + u >= e1) break;
+      const double dx = min_image(px[u] - xi, g.L[0], g.half[0], g.per[0]);
+      const double dy = min_image(py[u] - yi, g.L[1], g.half[1], g.per[1]);
+      const double dz = min_image(pz[u] - zi, g.L[2], g.half[2], g.per[2]);
+      const bool ok = j[u] != i && mob[u] && sq_dist_exact(dx, dy, dz) < A.r2om;
+      ctmp[e + u] = ok ? j[u] : -1;
+      mine += ok ? 1 : 0;
     }
   }
+  return mine;
 }
 
 // One workgroup per colour cell of one colour: the cell's corrections, one after the other.
@@ -219,6 +279,8 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
   __shared__ int seg[kSegCap];
   __shared__ unsigned long long key[kCandCap];
   __shared__ int cand[kCandCap];
+  __shared__ int ctmp[kCandCap];
+  __shared__ int st_base[kStCap], st_pref[kStCap + 1];
   __shared__ int hist[256];
   __shared__ double shd[kThThreads / kWave];
   __shared__ int shi[kThThreads / kWave];
@@ -258,23 +320,30 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
   for (int t = 0; t < m; ++t) {
     const int i = seg[t];
     const double xi = A.pos[i], yi = A.pos[(size_t)A.n + i], zi = A.pos[2 * (size_t)A.n + i];
-    // candidates: count, scan, write in a deterministic order
-    int mine = 0;
-    for_candidates(A, sg, i, xi, yi, zi, tid, kThThreads, [&](int) { ++mine; });
-    int total = 0;
-    const int off = block_exclusive(mine, shi, &total);
-    if (total > kCandCap) {
+    // candidates in stencil-slot order: mark, scan, compact
+    const int M = stencil_slots(A, sg, xi, yi, zi, st_base, st_pref, shi);
+    if (M > kCandCap) {
       if (tid == 0) atomicAdd(&A.counters[2], 1);
       __syncthreads();
       continue;
     }
+    const int mine = mark_candidates(A, sg, i, xi, yi, zi, st_base, st_pref, sg.span[0] * sg.span[1] * sg.span[2],
+                                     M, ctmp);
+    int total = 0;
+    const int off = block_exclusive(mine, shi, &total);
     const bool draw = total > need_max;
-    int w = off;
-    for_candidates(A, sg, i, xi, yi, zi, tid, kThThreads, [&](int j) {
-      cand[w] = j;
-      if (draw) key[w] = philox_first_word((unsigned long long)i, (unsigned long long)j, A.step, 0ull, A.seed, 0ull);
-      ++w;
-    });
+    {
+      const int per = (M + kThThreads - 1) / kThThreads;
+      const int e0 = tid * per, e1 = e0 + per < M ? e0 + per : M;
+      int w = off;
+      for (int e = e0; e < e1; ++e) {
+        const int j = ctmp[e];
+        if (j < 0) continue;
+        cand[w] = j;
+        if (draw) key[w] = philox_first_word((unsigned long long)i, (unsigned long long)j, A.step, 0ull, A.seed, 0ull);
+        ++w;
+      }
+    }
     __syncthreads();
     // selection of the need_max smallest (priority, index) by radix select on the priority
     if (draw) {
@@ -287,18 +356,18 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
         for (int k = tid; k < total; k += kThThreads)
           if ((key[k] & mask) == prefix) atomicAdd(&hist[(key[k] >> shift) & 255ull], 1);
         __syncthreads();
-        if (tid == 0) {
-          int cum = 0, bsel = 0;
-          for (int q = 0; q < 256; ++q) {
-            if (cum + hist[q] >= need) {
-              bsel = q;
-              break;
-            }
-            cum += hist[q];
+        {
+          // the bucket holding the need-th smallest key: thread = bucket
+          static_assert(kThThreads == 256, "one thread per bucket");
+          const int h = hist[tid];
+          int all = 0;
+          const int cum = block_exclusive(h, shi, &all);
+          // (need = 0, |Omega| = 1: bucket 0, nothing below it)
+          if ((cum < need && cum + h >= need) || (need == 0 && tid == 0)) {
+            sel_state[0] = tid;
+            sel_state[1] = cum;
+            sel_state[2] = h;
           }
-          sel_state[0] = bsel;
-          sel_state[1] = cum;
-          sel_state[2] = hist[bsel];
         }
         __syncthreads();
         const int bsel = sel_state[0], below = sel_state[1], inb = sel_state[2];

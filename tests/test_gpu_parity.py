@@ -87,6 +87,23 @@ def test_neighbor_rows_16k_with_vacancies(ops_ctx):
     assert np.array_equal(flat, idx)
 
 
+@pytest.mark.parametrize("r_list", [6.5, 6.8])
+def test_neighbor_rows_wide_cells(ops_ctx, r_list):
+    """Rows longer than 64 entries, and cells so wide (three per axis of a 25.3-A box)
+    that the 27 neighbouring cells hold all 1,370 atoms: more candidates than a block
+    stages, read from global memory instead."""
+    ops, ctx = ops_ctx
+    _case(f"neighbors wide cells r_list {r_list}")
+    s = configs.bulk(7, seed=12, temperature=300.0, vacancies=2)
+    nl = ops.build_neighbors(ctx, ops.device_atoms(s), r_list, max_nb=128)
+    off, idx = geometry.neighbor_csr(s.pos, s.lo, s.hi, s.periodic, r_list)
+    cnt, rows = _rows(nl)
+    assert np.diff(off).max() > 64
+    assert np.array_equal(cnt, np.diff(off))
+    for i in range(s.n):
+        assert np.array_equal(rows[: cnt[i], i], idx[off[i]:off[i + 1]]), i
+
+
 def test_neighbor_capacity_error(ops_ctx):
     ops, ctx = ops_ctx
     from paper_2411_03002_amd import binding
