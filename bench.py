@@ -562,9 +562,6 @@ def main():
         "rebuilds": int(st_a["rebuilds"]),
         "class_ms_per_step": class_times(tim_a, K),
     }
-    if args.profile_only:
-        print(json.dumps(result), flush=True)
-        return
     # live per-kernel roofline of the adaptive timed region
     nb_avg = 60.0
     n_act = st_a["prof"]["ace_atoms"] / st_a["prof"]["steps"]
@@ -578,6 +575,9 @@ def main():
     roofs = {k: roofline_for(k, models[k], *prof_a[k], algo=algo_work(k, n_act)) for k in prof_a if k in models}
     result["roofline"] = roofs.get(dom)
     result["roofline_all"] = roofs
+    if args.profile_only:
+        print(json.dumps(result), flush=True)
+        return
 
     # float32 vs float64 ACE on the detected atoms, and the method error (hybrid vs full
     # ACE, both float64) on the atoms with w = 1, at the thermal start

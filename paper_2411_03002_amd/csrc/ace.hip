@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
   }
   __syncthreads();
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform across the wave
   const int t = lane % TILE;
   const bool own = lane < TILE;
   // pairs are sorted by coupling type and dealt round-robin, so all waves of a block run
@@ -705,7 +705,9 @@ __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ A
   constexpr int LM = (LMAX + 1) * (LMAX + 1);
   constexpr int TILE = 64;
   constexpr int kMaxK = 12;
-  const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform across the wave: said so, the column's l is too and the
+  // weights become scalar loads (otherwise every lane loads the same weight)
+  const int t = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const T* Ab = Abg + (size_t)blockIdx.x * na * TILE;
   T* B = Bg + (size_t)blockIdx.x * na * TILE;
   for (int lm = wv; lm < LM; lm += 4) {
@@ -1200,7 +1202,7 @@ __global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag
   stage_tile<T, TILE>(Ag, As, q0, n_act, na, NW * 64);
   __syncthreads();
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform across the wave
   const int t = lane % TILE;
   Acc<T> acc{T(0), T(0), T(0), T(0)};
   if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
@@ -1256,7 +1258,7 @@ __global__ void __launch_bounds__(NW * 64, G <= 3 ? 2 : 1) k_ace_adjoint(const T
   stage_tile<T, TILE>(Ag, As, q0, n_act, na, NW * 64);
   __syncthreads();
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform across the wave
   const int t = lane % TILE;
   const T fp = fp_in[q0 + t];
   T* Abt = Abg + (size_t)blockIdx.x * na * TILE;
