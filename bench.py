@@ -41,12 +41,49 @@ PEAK_FP64_TFLOPS = 78.6
 GAUNT_TERMS = {(10, 4): 211610, (8, 3): 33168}
 ALGO_FLOP_PER_TERM = {"ace.energy": 6.0, "ace.adjoint": 10.0}
 
-# Hardware counters of the dominant kernel class on the indentation block (rocprofv3
-# --pmc FETCH_SIZE, then WRITE_SIZE, KiB per dispatch summed over the launches of one
-# step), scaled to bytes by a 1 GiB device copy (fetch x2.0, write x1.0).  They hold only
-# for the kernel source they were measured on: ``source_sha256`` is checked at run time
-# and the traffic is reported as null when the source has changed since.
-COUNTERS = {}
+# Hardware counters per launch of each kernel class on the indentation block (rocprofv3
+# --pmc FETCH_SIZE, then WRITE_SIZE; KiB per launch, a class launch being one step of its
+# kernels), taken on `units` atoms (the active atoms for the ACE classes, all atoms
+# otherwise) and scaled to the workload timed here in proportion.  A 1 GiB device copy
+# reads as 524,308 KiB fetched and 1,048,576 KiB written: fetch counts are scaled by 2.0,
+# write counts by 1.0.  They hold only for the kernel source they were measured on:
+# `source_sha256` is checked at run time and the traffic is reported as null when the
+# source has changed since.
+COUNTERS = {
+    "ace.adjoint": {"fetch_kib": 3612770.5, "write_kib": 20965755.1, "units": 1137181,
+        "source": "paper_2411_03002_amd/csrc/ace.hip",
+        "source_sha256": "2f6568b63dce72e5053d40847ece4b7e086d9e5ff8e8d20184d7f4be5f61feb8"},
+    "ace.energy": {"fetch_kib": 579780.4, "write_kib": 16309.9, "units": 1137181,
+        "source": "paper_2411_03002_amd/csrc/ace.hip",
+        "source_sha256": "2f6568b63dce72e5053d40847ece4b7e086d9e5ff8e8d20184d7f4be5f61feb8"},
+    "ace.basis": {"fetch_kib": 395779.5, "write_kib": 1128297.6, "units": 1137181,
+        "source": "paper_2411_03002_amd/csrc/ace.hip",
+        "source_sha256": "2f6568b63dce72e5053d40847ece4b7e086d9e5ff8e8d20184d7f4be5f61feb8"},
+    "ace.force": {"fetch_kib": 976736.3, "write_kib": 2259585.5, "units": 1137181,
+        "source": "paper_2411_03002_amd/csrc/ace.hip",
+        "source_sha256": "2f6568b63dce72e5053d40847ece4b7e086d9e5ff8e8d20184d7f4be5f61feb8"},
+    "ace.backproject": {"fetch_kib": 555319.8, "write_kib": 1110562.5, "units": 1137181,
+        "source": "paper_2411_03002_amd/csrc/ace.hip",
+        "source_sha256": "2f6568b63dce72e5053d40847ece4b7e086d9e5ff8e8d20184d7f4be5f61feb8"},
+    "eam.density": {"fetch_kib": 623802.7, "write_kib": 125000.0, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/eam.hip",
+        "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
+    "eam.force": {"fetch_kib": 821277.8, "write_kib": 93750.0, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/eam.hip",
+        "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
+    "nbr.build": {"fetch_kib": 185412.8, "write_kib": 1216033.1, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/neighbors.hip",
+        "source_sha256": "03850caf5368f1ef36e179c1c420166396fada9283c442c89b4a770226a9453a"},
+    "prec.csp": {"fetch_kib": 1010303.8, "write_kib": 94062.5, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/precision.hip",
+        "source_sha256": "a7812fbabcc117a32a09dbbcdac85f910fe171945d9873000a3090c270592727"},
+    "md.kick_drift": {"fetch_kib": 187625.9, "write_kib": 185640.1, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/md.hip",
+        "source_sha256": "81044060b49f66f05856522b0929ef8df4df87afeb3afbffba3140cc5a0ef65e"},
+    "blend": {"fetch_kib": 132651.1, "write_kib": 125066.2, "units": 4000000,
+        "source": "paper_2411_03002_amd/csrc/blend.hip",
+        "source_sha256": "bee68539ddde7cd4a46af5411dc13e285eed2822a8bc933241cbee66b16952d9"},
+}
 
 
 def parse():
@@ -130,16 +167,17 @@ def _source_sha(rel):
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_for(name, launches_per_step):
-    """HBM bytes per launch of ``name`` from the committed counter readings, or None when
-    there are none or the kernel source changed after they were taken."""
+def traffic_for(name, units):
+    """HBM bytes per launch of ``name`` on ``units`` atoms from the committed counter
+    readings, or None when there are none or the kernel source changed after they were
+    taken."""
     c = COUNTERS.get(name)
-    if not c or _source_sha(c["source"]) != c["source_sha256"]:
+    if not c or not units or _source_sha(c["source"]) != c["source_sha256"]:
         return None
-    return (2.0 * c["fetch_kib"] + 1.0 * c["write_kib"]) * 1024.0 / max(launches_per_step, 1)
+    return (2.0 * c["fetch_kib"] + 1.0 * c["write_kib"]) * 1024.0 * units / c["units"]
 
 
-def roofline_for(name, model, launches, total_ms, algo=None, launches_per_step=1):
+def roofline_for(name, model, launches, total_ms, algo=None, units=None):
     """Roofline entry of one kernel class from its measured average launch time.
 
     ``model`` = (bound, amount per launch, unit) as implemented; ``algo`` (optional) the
@@ -150,12 +188,12 @@ def roofline_for(name, model, launches, total_ms, algo=None, launches_per_step=1
     if unit == "byte":
         achieved = amount / avg_s / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name, launches_per_step),
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name, units),
                 "avg_ms": avg_s * 1e3, "work_per_launch": amount}
     work = amount if algo is None else algo
     achieved = work / avg_s / 1e12
     out = {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_for(name, launches_per_step),
+           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_for(name, units),
            "avg_ms": avg_s * 1e3, "work_per_launch": work}
     if algo is not None:
         ex = amount / avg_s / 1e12
@@ -572,7 +610,8 @@ def main():
     dom = max(prof_a.items(), key=lambda kv: kv[1][1])[0]
     result["kernels"] = kern
     result["dominant_kernel"] = dom
-    roofs = {k: roofline_for(k, models[k], *prof_a[k], algo=algo_work(k, n_act)) for k in prof_a if k in models}
+    roofs = {k: roofline_for(k, models[k], *prof_a[k], algo=algo_work(k, n_act),
+                             units=n_act if k.startswith("ace.") else n) for k in prof_a if k in models}
     result["roofline"] = roofs.get(dom)
     result["roofline_all"] = roofs
     if args.profile_only:
@@ -679,6 +718,7 @@ def main():
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof_e.items()
                         if k.startswith("eam.")},
             "roofline": {k: roofline_for(k, m6[k], *prof_e[k]) for k in ("eam.density", "eam.force") if k in prof_e},
+            "note": "counter traffic was taken on the synthetic form's 5.5-A list, so none is given here",
         }
         del nl6
         torch.cuda.empty_cache()
@@ -696,7 +736,7 @@ def main():
         for k in ("ace.energy", "ace.adjoint"):
             if k in prof_f:
                 result[f"roofline_full_ace_{k.split('.')[1]}"] = roofline_for(k, mf[k], *prof_f[k],
-                                                                            algo=algo_work(k, n_f))
+                                                                            algo=algo_work(k, n_f), units=n_f)
         result["kernels_full_ace"] = {k: {"launches": v[0], "total_ms": v[1], "avg_ms": v[1] / max(v[0], 1)}
                                       for k, v in prof_f.items()}
         log(f"full ACE {dt_f / KF * 1e3:.2f} ms/step, {full:.4g} atom-steps/s, ratio {adaptive / full:.2f}")

@@ -189,9 +189,9 @@ __global__ void __launch_bounds__(64) k_ace_basis(const double* __restrict__ pos
     for (int a = 0; a < LM; ++a) S[a] = T(0);
     if (k < cnt) {
       const int j = idx[(size_t)k * n + i];
-      const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
-      const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
-      const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
+      const double dx = min_image_sel(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image_sel(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image_sel(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       const double ird = rsq_nr(r2);
       const double rd = r2 * ird;
@@ -799,9 +799,9 @@ __global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos
     const int k = c0 + lane;
     if (k < cnt) {
       const int j = idx[(size_t)k * n + i];
-      const double dx = min_image(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
-      const double dy = min_image(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
-      const double dz = min_image(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
+      const double dx = min_image_sel(pos[j] - xi, b.L[0], b.half[0], b.per[0]);
+      const double dy = min_image_sel(pos[(size_t)n + j] - yi, b.L[1], b.half[1], b.per[1]);
+      const double dz = min_image_sel(pos[2 * (size_t)n + j] - zi, b.L[2], b.half[2], b.per[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       double gx = 0.0, gy = 0.0, gz = 0.0;
       const double ird = rsq_nr(r2);

@@ -23,13 +23,24 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 // Minimum image of d = x_j - x_i along one axis of length L (both coordinates in
 // [lo, hi)): d -= L if d >= L/2; d += L if d < -L/2.  (Written as branches: few pairs
-// wrap, and a branch no lane takes costs less than forming both shifted values.)
+// wrap, and in the thread-per-atom gathers a branch no lane takes costs less than forming
+// both shifted values.)
 __device__ __forceinline__ double min_image(double d, double L, double half, int periodic) {
   if (periodic) {
     if (d >= half) d -= L;
     else if (d < -half) d += L;
   }
   return d;
+}
+
+// The same value formed without branches (both shifted values and selects): cheaper in the
+// ACE basis and force kernels (a wave per atom, lanes over its neighbours), where it took
+// 8-9% off each.
+__device__ __forceinline__ double min_image_sel(double d, double L, double half, int periodic) {
+  const double dm = d - L, dp = d + L;
+  double r = d >= half ? dm : d;
+  r = d < -half ? dp : r;
+  return periodic ? r : d;
 }
 
 // (dx*dx + dy*dy) + dz*dz with every product and sum rounded separately.

@@ -180,6 +180,7 @@ struct ThermoArgs {
 };
 
 constexpr int kStCap = 1344;  // stencil cells of one atom (at most 11 per axis)
+constexpr int kPer = kCandCap / kThThreads;  // candidate slots per thread
 
 // The search-grid stencil of the atom at (xi, yi, zi): for stencil cell q < total, the
 // first slot of its atoms in the cell list (st_base) and the exclusive prefix of the
@@ -225,8 +226,8 @@ __device__ int stencil_slots(const ThermoArgs& A, const SearchGrid& g, double xi
 }
 
 // The candidates of atom i (mobile j != i with r_ij^2 < r_omega^2) in slot order: every
-// thread tests a contiguous range of slots (four loads in flight at a time) and marks
-// them in ctmp (the atom index, or -1); returns the thread's count.
+// thread tests a contiguous range of at most kPer slots (all its loads in flight together)
+// and marks them in ctmp (the atom index, or -1); returns the thread's count.
 __device__ int mark_candidates(const ThermoArgs& A, const SearchGrid& g, int i, double xi, double yi, double zi,
                                const int* st_base, const int* st_pref, int total, int M, int* ctmp) {
   const int per = (M + kThThreads - 1) / kThThreads;
@@ -240,29 +241,29 @@ __device__ int mark_candidates(const ThermoArgs& A, const SearchGrid& g, int i, 
     else hi = mid - 1;
   }
   int q = lo, mine = 0;
-  for (int e = e0; e < e1; e += 4) {
-    int j[4];
+  const int e = e0;
+  int j[kPer];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      j[u] = -1;
-      if (e + u < e1) {
-        while (st_pref[q + 1] <= e + u) ++q;
-        j[u] = A.cell_atoms[st_base[q] + (e + u - st_pref[q])];
-      }
+  for (int u = 0; u < kPer; ++u) {
+    j[u] = -1;
+    if (e + u < e1) {
+      while (st_pref[q + 1] <= e + u) ++q;
+      j[u] = A.cell_atoms[st_base[q] + (e + u - st_pref[q])];
     }
-    double px[4], py[4], pz[4];
-    bool mob[4];
+  }
+  double px[kPer], py[kPer], pz[kPer];
+  bool mob[kPer];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int jj = j[u] < 0 ? i : j[u];
-      px[u] = A.pos[jj];
-      py[u] = A.pos[(size_t)A.n + jj];
-      pz[u] = A.pos[2 * (size_t)A.n + jj];
-      mob[u] = !(A.frozen && A.frozen[jj]);
-    }
+  for (int u = 0; u < kPer; ++u) {
+    const int jj = j[u] < 0 ? i : j[u];
+    px[u] = A.pos[jj];
+    py[u] = A.pos[(size_t)A.n + jj];
+    pz[u] = A.pos[2 * (size_t)A.n + jj];
+    mob[u] = !(A.frozen && A.frozen[jj]);
+  }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (e + u >= e1) break;
+  for (int u = 0; u < kPer; ++u) {
+    if (e + u < e1) {
       const double dx = min_image(px[u] - xi, g.L[0], g.half[0], g.per[0]);
       const double dy = min_image(py[u] - yi, g.L[1], g.half[1], g.per[1]);
       const double dz = min_image(pz[u] - zi, g.L[2], g.half[2], g.per[2]);
@@ -402,20 +403,33 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
       }
       __syncthreads();
     }
-    // centre-of-mass velocity of the group (atom i and the taken candidates)
+    // centre-of-mass velocity of the group (atom i and the taken candidates); every thread
+    // holds the velocities of its candidates k = tid + kThThreads u in registers
     const int gsize = 1 + (draw ? need_max : total);
+    int jk[kPer];
+    double vx[kPer], vy[kPer], vz[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + kThThreads * u;
+      jk[u] = k < total ? cand[k] : -1;
+      const int jj = jk[u] < 0 ? i : jk[u];
+      vx[u] = A.vel[jj];
+      vy[u] = A.vel[(size_t)A.n + jj];
+      vz[u] = A.vel[2 * (size_t)A.n + jj];
+    }
+    const double vix = A.vel[i], viy = A.vel[(size_t)A.n + i], viz = A.vel[2 * (size_t)A.n + i];
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (tid == 0) {
-      sx = A.vel[i];
-      sy = A.vel[(size_t)A.n + i];
-      sz = A.vel[2 * (size_t)A.n + i];
+      sx = vix;
+      sy = viy;
+      sz = viz;
     }
-    for (int k = tid; k < total; k += kThThreads) {
-      const int j = cand[k];
-      if (j < 0) continue;
-      sx += A.vel[j];
-      sy += A.vel[(size_t)A.n + j];
-      sz += A.vel[2 * (size_t)A.n + j];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (jk[u] < 0) continue;
+      sx += vx[u];
+      sy += vy[u];
+      sz += vz[u];
     }
     const double inv_g = 1.0 / (double)gsize;
     const double vcx = block_sum(sx, shd) * inv_g;
@@ -423,13 +437,13 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
     const double vcz = block_sum(sz, shd) * inv_g;
     double kr = 0.0;
     if (tid == 0) {
-      const double ax = A.vel[i] - vcx, ay = A.vel[(size_t)A.n + i] - vcy, az = A.vel[2 * (size_t)A.n + i] - vcz;
+      const double ax = vix - vcx, ay = viy - vcy, az = viz - vcz;
       kr = ax * ax + ay * ay + az * az;
     }
-    for (int k = tid; k < total; k += kThThreads) {
-      const int j = cand[k];
-      if (j < 0) continue;
-      const double ax = A.vel[j] - vcx, ay = A.vel[(size_t)A.n + j] - vcy, az = A.vel[2 * (size_t)A.n + j] - vcz;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (jk[u] < 0) continue;
+      const double ax = vx[u] - vcx, ay = vy[u] - vcy, az = vz[u] - vcz;
       kr += ax * ax + ay * ay + az * az;
     }
     const double k_rel = A.half_m_over_conv * block_sum(kr, shd);
@@ -441,17 +455,18 @@ __global__ void __launch_bounds__(kThThreads) k_th_rescale(ThermoArgs A, SearchG
     }
     const double beta = sqrt(rad);
     if (tid == 0) {
-      A.vel[i] = vcx + beta * (A.vel[i] - vcx);
-      A.vel[(size_t)A.n + i] = vcy + beta * (A.vel[(size_t)A.n + i] - vcy);
-      A.vel[2 * (size_t)A.n + i] = vcz + beta * (A.vel[2 * (size_t)A.n + i] - vcz);
+      A.vel[i] = vcx + beta * (vix - vcx);
+      A.vel[(size_t)A.n + i] = vcy + beta * (viy - vcy);
+      A.vel[2 * (size_t)A.n + i] = vcz + beta * (viz - vcz);
       atomicAdd(&A.counters[0], 1);
     }
-    for (int k = tid; k < total; k += kThThreads) {
-      const int j = cand[k];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int j = jk[u];
       if (j < 0) continue;
-      A.vel[j] = vcx + beta * (A.vel[j] - vcx);
-      A.vel[(size_t)A.n + j] = vcy + beta * (A.vel[(size_t)A.n + j] - vcy);
-      A.vel[2 * (size_t)A.n + j] = vcz + beta * (A.vel[2 * (size_t)A.n + j] - vcz);
+      A.vel[j] = vcx + beta * (vx[u] - vcx);
+      A.vel[(size_t)A.n + j] = vcy + beta * (vy[u] - vcy);
+      A.vel[2 * (size_t)A.n + j] = vcz + beta * (vz[u] - vcz);
     }
     __threadfence_block();
     __syncthreads();
