@@ -285,7 +285,8 @@ apx_status apx_blend_noalloc(apx_ctx* ctx, int64_t n, const double* w, const dou
 
 /* ---------------------------------------------------------- integration */
 #define APX_MODE_ADAPTIVE 0 /* EAM everywhere, ACE where w > 0, w from the criterion */
-#define APX_MODE_FULL_ACE 1 /* w = 1 for every mobile atom, no EAM, no detection */
+#define APX_MODE_FULL_ACE 1 /* w = 1 for every atom, no EAM, no detection (frozen atoms keep their
+                             site energies, which depend on mobile neighbours) */
 #define APX_MODE_EAM 2      /* w = 0, no ACE, no detection */
 
 /* ------------------------------------------------------- local thermostat */

@@ -66,7 +66,7 @@ struct apx_ctx {
   std::string err;
   // scratch owned by the context
   apx::DevBuf cell_id, cell_count, cell_start, cell_fill, cell_atoms;
-  apx::DevBuf scan_tmp, flags, itmp, itmp2, dtmp, ace_buf;
+  apx::DevBuf scan_tmp, flags, itmp, itmp2, dtmp, ace_buf, thermo_grp;
   int* host_pinned = nullptr;  // small pinned staging area for readbacks
   // optional per-kernel timing with HIP events on the context stream
   bool prof = false;

@@ -272,11 +272,17 @@ __global__ void k_pack_bf16(const float* __restrict__ P, unsigned short* __restr
   if (e < kH) wb[kH * 16 + 2 * kH * kH + e] = bf16_rne(P[kOffW4 + e]);
 }
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ v4f mfma_bf16_16x16x32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
 // One wave evaluates 16 atoms: every hidden layer is a [16 x K] x [K x 64] product on the
-// 16x16x16 bfloat16 matrix cores (four output tiles, K/16 steps), bias + tanh in float32,
+// 16x16x32 bfloat16 matrix cores of gfx950 (four output tiles, K/32 steps; lane = row or
+// column (lane % 16) and a group of eight K values (lane / 16)), bias + tanh in float32,
 // the activations rounded to bfloat16 in LDS for the next layer.
 __global__ void __launch_bounds__(256) k_mlp_bf16(const float* __restrict__ feat, int n, const float* __restrict__ P,
                                                   const unsigned short* __restrict__ wb, Std4 st,
@@ -287,12 +293,12 @@ __global__ void __launch_bounds__(256) k_mlp_bf16(const float* __restrict__ feat
   const int a0 = (blockIdx.x * 4 + wv) * 16;
   const int ri = lane & 15;   // row (atom) of A, column (neuron) of B and D
   const int kq = lane >> 4;   // k quad
-  // inputs, standardised and rounded, K padded to 16
+  // inputs, standardised and rounded, K padded to 32 (the weights hold 16 columns)
   {
-    v4s a;
+    v8s a;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = 4 * kq + r;
+    for (int r = 0; r < 8; ++r) {
+      const int k = 8 * kq + r;
       float x = 0.f;
       if (k < kIn && a0 + ri < n) x = (feat[4 * (size_t)(a0 + ri) + k] - st.mu[k]) / st.sd[k];
       a[r] = (short)bf16_rne(x);
@@ -300,11 +306,14 @@ __global__ void __launch_bounds__(256) k_mlp_bf16(const float* __restrict__ feat
     const unsigned short* W1 = wb;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      v4s bv;
+      v8s bv;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bv[r] = (short)W1[(nt * 16 + ri) * 16 + 4 * kq + r];
+      for (int r = 0; r < 8; ++r) {
+        const int k = 8 * kq + r;
+        bv[r] = k < 16 ? (short)W1[(nt * 16 + ri) * 16 + k] : (short)0;
+      }
       v4f c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, c, 0, 0, 0);
+      c = mfma_bf16_16x16x32(a, bv, c);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = nt * 16 + ri;
@@ -321,16 +330,16 @@ __global__ void __launch_bounds__(256) k_mlp_bf16(const float* __restrict__ feat
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) c[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      v4s a;
+    for (int ks = 0; ks < kH / 32; ++ks) {
+      v8s a;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = (short)act[wv][ri][16 * ks + 4 * kq + r];
+      for (int r = 0; r < 8; ++r) a[r] = (short)act[wv][ri][32 * ks + 8 * kq + r];
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        v4s bv;
+        v8s bv;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bv[r] = (short)Wl[(nt * 16 + ri) * kH + 16 * ks + 4 * kq + r];
-        c[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, c[nt], 0, 0, 0);
+        for (int r = 0; r < 8; ++r) bv[r] = (short)Wl[(nt * 16 + ri) * kH + 32 * ks + 8 * kq + r];
+        c[nt] = mfma_bf16_16x16x32(a, bv, c[nt]);
       }
     }
     __syncthreads();
