@@ -50,37 +50,37 @@ ALGO_FLOP_PER_TERM = {"ace.energy": 6.0, "ace.adjoint": 10.0}
 # `source_sha256` is checked at run time and the traffic is reported as null when the
 # source has changed since.
 COUNTERS = {
-    "ace.adjoint": {"fetch_kib": 3615317.5, "write_kib": 20966008.9, "units": 1137181,
+    "ace.adjoint": {"fetch_kib": 3614509.5, "write_kib": 20966341.3, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "b0b3a4f9de2eaf9df7644c569807640ba6e000ddcc8dc1465931b478567fd0de"},
-    "ace.energy": {"fetch_kib": 579844.9, "write_kib": 16309.9, "units": 1137181,
+        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
+    "ace.energy": {"fetch_kib": 581009.2, "write_kib": 85244.1, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "b0b3a4f9de2eaf9df7644c569807640ba6e000ddcc8dc1465931b478567fd0de"},
-    "ace.basis": {"fetch_kib": 394948.7, "write_kib": 1128297.9, "units": 1137181,
+        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
+    "ace.basis": {"fetch_kib": 394959.7, "write_kib": 1128297.7, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "b0b3a4f9de2eaf9df7644c569807640ba6e000ddcc8dc1465931b478567fd0de"},
-    "ace.force": {"fetch_kib": 972938.5, "write_kib": 2259585.5, "units": 1137181,
+        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
+    "ace.force": {"fetch_kib": 975862.5, "write_kib": 2616184.6, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "b0b3a4f9de2eaf9df7644c569807640ba6e000ddcc8dc1465931b478567fd0de"},
+        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
     "ace.backproject": {"fetch_kib": 555319.8, "write_kib": 1110562.5, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "b0b3a4f9de2eaf9df7644c569807640ba6e000ddcc8dc1465931b478567fd0de"},
-    "eam.density": {"fetch_kib": 623521.9, "write_kib": 125000.0, "units": 4000000,
+        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
+    "eam.density": {"fetch_kib": 624017.4, "write_kib": 125000.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "eam.force": {"fetch_kib": 821472.9, "write_kib": 93750.0, "units": 4000000,
+    "eam.force": {"fetch_kib": 821649.1, "write_kib": 93750.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "nbr.build": {"fetch_kib": 185413.4, "write_kib": 1216103.3, "units": 4000000,
+    "nbr.build": {"fetch_kib": 185410.2, "write_kib": 1215818.6, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/neighbors.hip",
         "source_sha256": "03850caf5368f1ef36e179c1c420166396fada9283c442c89b4a770226a9453a"},
-    "prec.csp": {"fetch_kib": 1008385.4, "write_kib": 94062.5, "units": 4000000,
+    "prec.csp": {"fetch_kib": 1009326.3, "write_kib": 94062.5, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/precision.hip",
         "source_sha256": "a7812fbabcc117a32a09dbbcdac85f910fe171945d9873000a3090c270592727"},
-    "md.kick_drift": {"fetch_kib": 187626.5, "write_kib": 185642.6, "units": 4000000,
+    "md.kick_drift": {"fetch_kib": 187625.0, "write_kib": 185636.2, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/md.hip",
         "source_sha256": "81044060b49f66f05856522b0929ef8df4df87afeb3afbffba3140cc5a0ef65e"},
-    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.8, "units": 4000000,
+    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.5, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/blend.hip",
         "source_sha256": "bee68539ddde7cd4a46af5411dc13e285eed2822a8bc933241cbee66b16952d9"},
 }

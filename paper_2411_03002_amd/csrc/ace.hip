@@ -18,6 +18,7 @@
 //  3. k_ace_force    one wave per active atom: back-projection of Abar through Wp, then
 //                    per neighbour the gradient of sum Abar'' g_k S_lm, scattered as
 //                    F_j -= w_i dE_i/dr_ij, F_i += w_i dE_i/dr_ij (float64 atomics).
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -735,8 +736,10 @@ struct ForceLds {
   static constexpr int KP = (NMAX * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
 };
 
+// Float32 is held to 128 VGPRs, four waves per SIMD (a few registers spill; three waves left
+// the gathers' latency exposed).
 template <class T, int LMAX, int NMAX>
-__global__ void __launch_bounds__(64) k_ace_force(const double* __restrict__ pos, int n, BoxDev b,
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 1) k_ace_force(const double* __restrict__ pos, int n, BoxDev b,
                                                   const int* __restrict__ count, const int* __restrict__ idx,
                                                   int max_nb, const int* __restrict__ active, int n_act, int K,
                                                   T rc, T inv_h, double rc2, const T* __restrict__ Wp, AnchorDev an,
@@ -1189,14 +1192,14 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Ag, T* As, int 
 // label pairs dealt round-robin to the waves, compensated sums of c1.B and c2.B, then
 // E_i = phi1 + F_eps(phi2) (+ anchor) and the embedding slope F_eps'(phi2) for the adjoint.
 template <class T, int LMAX, int NMAX, int TILE, int NW, bool COMP>
-__global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag, int n_act, int na, int n_max,
+__global__ void __launch_bounds__(NW * 64, NW / 2) k_ace_energy(const T* __restrict__ Ag, int n_act, int na, int n_max,
                                                         AceTables<T> tb, int nb1, int nb2, T eps,
                                                         const double* __restrict__ e_anch,
                                                         const int* __restrict__ active, double* __restrict__ e_site,
                                                         T* __restrict__ fp_out) {
   extern __shared__ double smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
-  T* red = As + (size_t)na * (TILE + 1);  // [NW][4][TILE]
+  T* red = As;  // [NW][4][TILE], over the tile once every wave is done with it
   const int tid = threadIdx.x;
   const int q0 = blockIdx.x * TILE;
   stage_tile<T, TILE>(Ag, As, q0, n_act, na, NW * 64);
@@ -1218,6 +1221,7 @@ __global__ void __launch_bounds__(NW * 64) k_ace_energy(const T* __restrict__ Ag
     }
 #undef APX_FWD
   }
+  __syncthreads();
   if (lane < TILE) {
     red[(wv * 4 + 0) * TILE + t] = acc.s1;
     red[(wv * 4 + 1) * TILE + t] = acc.e1;
@@ -1386,9 +1390,11 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
       APX_LAUNCH_CHECK(ctx);
     }
     const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
-    // the energy pass needs few registers: 8 waves share a staged tile
-    constexpr int NWE = 8;
-    const size_t ldse = sizeof(T) * ((size_t)na * (TILE + 1) + NWE * 4 * TILE);
+    // the energy pass needs few registers: 16 waves share a staged tile (at most 64 VGPRs,
+    // two tiles per CU, eight waves per SIMD at n_max 10, l_max 4; the reduction buffer
+    // reuses the tile)
+    constexpr int NWE = 16;
+    const size_t ldse = sizeof(T) * std::max((size_t)na * (TILE + 1), (size_t)NWE * 4 * TILE);
     const size_t ldsa = sizeof(T) * (size_t)na * (TILE + 1);
     auto energy = [&](auto kern) -> apx_status {
       if (ensure_lds(ctx, (const void*)kern, ldse) != APX_OK) return APX_EDEVICE;
@@ -1514,6 +1520,7 @@ apx_status ace_impl(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, c
   if (s != APX_OK) return s;
   if (!nl || !m) return fail(ctx, APX_EINVAL, "nl and model are required");
   if (nl->n != atoms->n) return fail(ctx, APX_EINVAL, "nlist size mismatch");
+  if (nl->max_nb < 1 || nl->max_nb > 128) return fail(ctx, APX_EINVAL, "nlist max_nb must be in 1..128");
   if (m->r_cut > nl->r_list || (m->anchored && m->anchor.r_cut > nl->r_list))
     return fail(ctx, APX_EINVAL, "ACE cutoff exceeds the neighbour-list cutoff");
   if (precision != APX_FP64 && precision != APX_FP32) return fail(ctx, APX_EINVAL, "precision must be APX_FP64 or APX_FP32");
