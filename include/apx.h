@@ -324,7 +324,8 @@ apx_status apx_thermostat_energy_errors(apx_ctx* ctx, int64_t n, const uint8_t* 
 typedef struct {
   double r_omega;      /* group radius, A */
   int32_t omega_max;   /* |Omega|, the largest group (Appendix F: 800) */
-  int32_t reserved;
+  int32_t group_batch; /* most groups drawn and held at once (0: as many as 1 GiB holds); the
+                          corrections and their order do not depend on it */
   uint64_t seed;       /* key of the group draw */
 } apx_thermo_params;
 

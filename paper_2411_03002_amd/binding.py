@@ -59,7 +59,7 @@ class AceDesc(C.Structure):
 
 
 class ThermoParams(C.Structure):
-    _fields_ = [("r_omega", C.c_double), ("omega_max", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+    _fields_ = [("r_omega", C.c_double), ("omega_max", C.c_int32), ("group_batch", C.c_int32), ("seed", C.c_uint64)]
 
 
 class MdParams(C.Structure):

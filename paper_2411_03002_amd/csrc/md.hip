@@ -400,7 +400,7 @@ extern "C" apx_status apx_md_create(apx_ctx* ctx, const apx_atoms* atoms, const 
   if (p->avg_window != APX_WINDOW_PAST && p->avg_window != APX_WINDOW_CURRENT)
     return fail(ctx, APX_EINVAL, "avg_window must be APX_WINDOW_PAST or APX_WINDOW_CURRENT");
   if (p->thermostat != 0 && p->thermostat != 1) return fail(ctx, APX_EINVAL, "thermostat must be 0 or 1");
-  if (p->thermostat && (!(p->thermo.r_omega > 0.0) || p->thermo.omega_max < 1))
+  if (p->thermostat && (!(p->thermo.r_omega > 0.0) || p->thermo.omega_max < 1 || p->thermo.group_batch < 0))
     return fail(ctx, APX_EINVAL, "thermostat needs r_omega > 0 and omega_max >= 1");
   apx_md* md = new apx_md();
   md->ctx = ctx;

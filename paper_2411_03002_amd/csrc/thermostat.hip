@@ -683,7 +683,8 @@ apx_status thermostat_correct(apx_ctx* ctx, const apx_atoms* atoms, double* vel,
   // then rescales them colour by colour (entries of one colour are contiguous, so the
   // corrections keep the order (colour, cell, atom))
   const int stride = std::max(1, std::min(kCandCap, p->omega_max - 1));
-  const long long batch = std::max(1LL, std::min<long long>(total, kGrpBytes / (4LL * (stride + 1))));
+  long long batch = std::max(1LL, std::min<long long>(total, kGrpBytes / (4LL * (stride + 1))));
+  if (p->group_batch > 0 && p->group_batch < batch) batch = p->group_batch;
   APX_ALLOC(ctx, ctx->thermo_grp, sizeof(int) * (size_t)batch * (stride + 1));
   int* grp = ctx->thermo_grp.as<int>();
   int* gsz = grp + (size_t)batch * stride;
@@ -738,6 +739,7 @@ extern "C" apx_status apx_thermostat_correct(apx_ctx* ctx, const apx_atoms* atom
   if (atoms->n > 0 && (!vel || !dE)) return fail(ctx, APX_EINVAL, "vel and dE are required");
   if (!(p->r_omega > 0.0) || !(mass > 0.0)) return fail(ctx, APX_EINVAL, "r_omega and mass must be positive");
   if (p->omega_max < 1) return fail(ctx, APX_EINVAL, "omega_max must be at least 1");
+  if (p->group_batch < 0) return fail(ctx, APX_EINVAL, "group_batch must be >= 0");
   if (step < 0) return fail(ctx, APX_EINVAL, "step must be >= 0");
   s = thermostat_correct(ctx, atoms, vel, dE, p, step, mass, n_corrected, n_failed);
   if (s != APX_OK) return s;

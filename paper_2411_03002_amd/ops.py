@@ -464,6 +464,7 @@ def thermo_struct(p) -> B.ThermoParams:
     t = B.ThermoParams()
     t.r_omega = float(p["r_omega"])
     t.omega_max = int(p["omega_max"])
+    t.group_batch = int(p.get("group_batch", 0))
     t.seed = int(p["seed"])
     return t
 

@@ -112,6 +112,27 @@ def test_correction_parity(ops_ctx, case):
     assert not np.array_equal(v_ref, s.vel)
 
 
+@pytest.mark.parametrize("batch", [1, 37])
+def test_correction_parity_in_batches(ops_ctx, batch):
+    # groups drawn a few at a time: a colour cell's corrections span several batches, and
+    # the order (colour, cell, atom) and the result stay those of the oracle
+    ops, ctx = ops_ctx
+    _case(f"thermostat correction in batches of {batch} groups")
+    s = _bulk(12, 53)
+    dE = _inputs(s, 0.2, 7)
+    mobile = np.ones(s.n, bool)
+    v_ref = s.vel.copy()
+    rec = thermostat.correct(s.pos, s.lo, s.hi, s.periodic, v_ref, dE, mobile, M, 5.0, 50, 12345, 9)
+    atoms = ops.device_atoms(s)
+    vel = _dev(s.vel)
+    out = ops.thermostat_correct(ctx, atoms, vel, _dev(dE), dict(r_omega=5.0, omega_max=50, seed=12345,
+                                                                 group_batch=batch), 9, M)
+    v = vel.cpu().numpy()
+    print(f"{out['corrected']} corrections, max |dv| {np.abs(v - v_ref).max():.2e}", flush=True)
+    assert out["corrected"] == len(rec["order"]) - len(rec["failed"]) and out["failed"] == 0
+    assert np.abs(v - v_ref).max() < 1e-12 * np.abs(v_ref).max()
+
+
 def test_negative_radicand_reported(ops_ctx):
     ops, ctx = ops_ctx
     _case("thermostat negative radicand")
