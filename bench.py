@@ -50,37 +50,37 @@ ALGO_FLOP_PER_TERM = {"ace.energy": 6.0, "ace.adjoint": 10.0}
 # `source_sha256` is checked at run time and the traffic is reported as null when the
 # source has changed since.
 COUNTERS = {
-    "ace.adjoint": {"fetch_kib": 3614509.5, "write_kib": 20966341.3, "units": 1137181,
+    "ace.adjoint": {"fetch_kib": 3607058.3, "write_kib": 20966487.4, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
-    "ace.energy": {"fetch_kib": 581009.2, "write_kib": 85244.1, "units": 1137181,
+        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
+    "ace.energy": {"fetch_kib": 583367.7, "write_kib": 83578.8, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
-    "ace.basis": {"fetch_kib": 394959.7, "write_kib": 1128297.7, "units": 1137181,
+        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
+    "ace.basis": {"fetch_kib": 394951.0, "write_kib": 1128297.7, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
-    "ace.force": {"fetch_kib": 975862.5, "write_kib": 2616184.6, "units": 1137181,
+        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
+    "ace.force": {"fetch_kib": 976035.0, "write_kib": 2774930.7, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
-    "ace.backproject": {"fetch_kib": 555319.8, "write_kib": 1110562.5, "units": 1137181,
+        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
+    "ace.backproject": {"fetch_kib": 555311.9, "write_kib": 1110562.5, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "73beed470da5938464470efb40e5a8898522ab9b992df6068bc7c0eedffa75ad"},
-    "eam.density": {"fetch_kib": 624017.4, "write_kib": 125000.0, "units": 4000000,
+        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
+    "eam.density": {"fetch_kib": 623671.1, "write_kib": 125000.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "eam.force": {"fetch_kib": 821649.1, "write_kib": 93750.0, "units": 4000000,
+    "eam.force": {"fetch_kib": 821080.4, "write_kib": 93750.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "nbr.build": {"fetch_kib": 185410.2, "write_kib": 1215818.6, "units": 4000000,
+    "nbr.build": {"fetch_kib": 185411.5, "write_kib": 1216116.9, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/neighbors.hip",
         "source_sha256": "03850caf5368f1ef36e179c1c420166396fada9283c442c89b4a770226a9453a"},
-    "prec.csp": {"fetch_kib": 1009326.3, "write_kib": 94062.5, "units": 4000000,
+    "prec.csp": {"fetch_kib": 1010249.8, "write_kib": 94062.5, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/precision.hip",
         "source_sha256": "a7812fbabcc117a32a09dbbcdac85f910fe171945d9873000a3090c270592727"},
-    "md.kick_drift": {"fetch_kib": 187625.0, "write_kib": 185636.2, "units": 4000000,
+    "md.kick_drift": {"fetch_kib": 187627.4, "write_kib": 185642.1, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/md.hip",
-        "source_sha256": "81044060b49f66f05856522b0929ef8df4df87afeb3afbffba3140cc5a0ef65e"},
-    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.5, "units": 4000000,
+        "source_sha256": "8d7ab8f38bc1bd1152b97664fba70554bc73dfe7071e9989efb7c238119d3b53"},
+    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.8, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/blend.hip",
         "source_sha256": "bee68539ddde7cd4a46af5411dc13e285eed2822a8bc933241cbee66b16952d9"},
 }

@@ -625,10 +625,17 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
   const int pb = __builtin_amdgcn_readfirstlane(wv);
   // ------------------------------------------------------------ energy pass
   Acc<T> acc{T(0), T(0), T(0), T(0)};
+  // lane k < kPairRec holds word k of the wave's next pair record (one vector load a pair
+  // ahead, waited for only when the next pair reads it out)
+  int rv = 0;
+  if (pb < npairs && lane < kPairRec) rv = tb.pairs[pb * kPairRec + lane];
   if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
   for (int pi = pb; pi < npairs; pi += NW) {
-    const int* rec = tb.pairs + pi * kPairRec;
-    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+    int rec[kPairRec];
+#pragma unroll
+    for (int k = 0; k < kPairRec; ++k) rec[k] = __builtin_amdgcn_readlane(rv, k);
+    if (pi + NW < npairs && lane < kPairRec) rv = tb.pairs[(pi + NW) * kPairRec + lane];
+    const int type = rec[2];
 #define APX_FWD(A_, B_) \
   case A_ * (LMAX + 1) + B_: pair_fwd<T, LMAX, TILE, COMP, A_, B_>(As, rec, tb, t, acc); break;
     if constexpr (LMAX == 3) {
@@ -671,10 +678,14 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
       wfp = wdc * (double)fp;
     }
   }
+  if (pb < npairs && lane < kPairRec) rv = tb.pairs[pb * kPairRec + lane];
   if (wv == 0) low_order_bwd<T, TILE, DC>(As, Ab, tb, nb1, nb2, t, own, fp, wdc, wfp, dc1, dc2);
   for (int pi = pb; pi < npairs; pi += NW) {
-    const int* rec = tb.pairs + pi * kPairRec;
-    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+    int rec[kPairRec];
+#pragma unroll
+    for (int k = 0; k < kPairRec; ++k) rec[k] = __builtin_amdgcn_readlane(rv, k);
+    if (pi + NW < npairs && lane < kPairRec) rv = tb.pairs[(pi + NW) * kPairRec + lane];
+    const int type = rec[2];
 #define APX_BWD(A_, B_)                                                                                   \
   case A_ * (LMAX + 1) + B_:                                                                              \
     pair_bwd<T, LMAX, TILE, DC, A_, B_>(As, Ab, rec, tb, t, own, fp, wdc, wfp, dc1, dc2);                 \
@@ -1032,11 +1043,35 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
 #pragma unroll
   for (int m = 0; m < NR; ++m) accR[m] = T(0);
   int run_n = -1;
-  for (int e = eb; e < ee; ++e) {
+  // PF: the next entry's words are loaded while this entry computes (issued once this
+  // entry's LDS operands have arrived, so that their wait does not cover the prefetch)
+  constexpr bool PF = L <= kAdjPrefetchMaxL;
+  int nx_o1 = 0, nx_o2 = 0, nx_run = 0, nx_oth = 0;
+  T nx_c1[NMAX], nx_c2[NMAX];
+  auto fetch = [&](int e) {
     const int* E = tb.adj_i + (size_t)e * kAdjRec;
     const T* Ec = reinterpret_cast<const T*>(tb.adj_f) + (size_t)e * kAdjRec;
-    const int nrun = cld(E + 2);
-    const int noth = cld(E + 3);
+    nx_o1 = cld(E);
+    nx_o2 = cld(E + 1);
+    nx_run = cld(E + 2);
+    nx_oth = cld(E + 3);
+#pragma unroll
+    for (int n3 = 0; n3 < NMAX; ++n3) {
+      nx_c1[n3] = cld(Ec + kAdjC1 + n3);
+      nx_c2[n3] = cld(Ec + kAdjC2 + n3);
+    }
+  };
+  if (PF && eb < ee) fetch(eb);
+  for (int e = eb; e < ee; ++e) {
+    if (!PF) fetch(e);
+    const int nrun = nx_run;
+    const int noth = nx_oth;
+    T c1[NMAX], c2[NMAX];
+#pragma unroll
+    for (int n3 = 0; n3 < NMAX; ++n3) {
+      c1[n3] = nx_c1[n3];
+      c2[n3] = nx_c2[n3];
+    }
     if (nrun != run_n) {
       if (run_n >= 0) {
 #pragma unroll
@@ -1046,7 +1081,7 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
       for (int m = 0; m < NR; ++m) accR[m] = T(0);
       run_n = nrun;
     }
-    const int o1 = cld(E), o2 = cld(E + 1);
+    const int o1 = nx_o1, o2 = nx_o2;
     T a[N1], b[N2], P[NL], Pb[NL];
 #pragma unroll
     for (int m = 0; m < N1; ++m) a[m] = As[(o1 + m) * ST + t];
@@ -1058,12 +1093,17 @@ __device__ __forceinline__ void unit_bwd(const T* __restrict__ As, T* __restrict
       Pb[m] = T(0);
     }
     C::template fwd<T>(a, b, P);
+    if constexpr (PF) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (e + 1 < ee) fetch(e + 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int n3 = 0; n3 < NMAX; ++n3) {
       // the stream's coefficients are zero outside the pair's run of n3 and A3 is zero
       // beyond n_max: those terms add exact zeros, which costs less than branching on them
       {
-        const T d = fma(fp, cld(Ec + kAdjC2 + n3), cld(Ec + kAdjC1 + n3));
+        const T d = fma(fp, c2[n3], c1[n3]);
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           Pb[m] = fma(d, A3[n3][m], Pb[m]);
@@ -1208,10 +1248,17 @@ __global__ void __launch_bounds__(NW * 64, NW / 2) k_ace_energy(const T* __restr
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform across the wave
   const int t = lane % TILE;
   Acc<T> acc{T(0), T(0), T(0), T(0)};
+  // lane k < kPairRec holds word k of the wave's next pair record: one vector load per pair,
+  // issued a pair ahead and waited for only when the next pair reads it out
+  int rv = 0;
+  if (wv < tb.npairs && lane < kPairRec) rv = tb.pairs[wv * kPairRec + lane];
   if (wv == 0) low_order_fwd<T, TILE, COMP>(As, tb, nb1, nb2, t, acc);
   for (int pi = wv; pi < tb.npairs; pi += NW) {
-    const int* rec = tb.pairs + pi * kPairRec;
-    const int type = __builtin_amdgcn_readfirstlane(rec[2]);
+    int rec[kPairRec];
+#pragma unroll
+    for (int k = 0; k < kPairRec; ++k) rec[k] = __builtin_amdgcn_readlane(rv, k);
+    if (pi + NW < tb.npairs && lane < kPairRec) rv = tb.pairs[(pi + NW) * kPairRec + lane];
+    const int type = rec[2];
 #define APX_FWD(A_, B_) \
   case A_ * (LMAX + 1) + B_: pair_fwd_n<T, LMAX, NMAX, TILE, COMP, A_, B_>(As, rec, tb, t, n_max, acc); break;
     if constexpr (LMAX == 3) {

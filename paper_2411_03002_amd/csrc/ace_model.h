@@ -36,6 +36,9 @@ __host__ __device__ constexpr int unit_width(int g, int nmax) { return g >= 3 ? 
 // where there is no triple), so that a pair costs one batch of independent scalar loads.
 constexpr int kAdjRec = 32;
 constexpr int kAdjC1 = 8, kAdjC2 = 20;
+// Unit-adjoint degrees up to which the next pair-stream entry is loaded during the current one
+// (it takes 2 n_max + 4 scalar registers).
+constexpr int kAdjPrefetchMaxL = 1;
 // host copy of a stream entry: off1, off2, run label, other label, first n3, first triple,
 // number of triples
 constexpr int kAdjEnt = 7;
