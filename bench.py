@@ -50,37 +50,37 @@ ALGO_FLOP_PER_TERM = {"ace.energy": 6.0, "ace.adjoint": 10.0}
 # `source_sha256` is checked at run time and the traffic is reported as null when the
 # source has changed since.
 COUNTERS = {
-    "ace.adjoint": {"fetch_kib": 3607058.3, "write_kib": 20966487.4, "units": 1137181,
+    "ace.adjoint": {"fetch_kib": 3607605.0, "write_kib": 20966484.5, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
-    "ace.energy": {"fetch_kib": 583367.7, "write_kib": 83578.8, "units": 1137181,
+        "source_sha256": "5f9370f6cb936839c61624ac7032b0f06b53118e2e38365273338e5a8f75b3df"},
+    "ace.energy": {"fetch_kib": 582437.3, "write_kib": 83597.8, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
-    "ace.basis": {"fetch_kib": 394951.0, "write_kib": 1128297.7, "units": 1137181,
+        "source_sha256": "5f9370f6cb936839c61624ac7032b0f06b53118e2e38365273338e5a8f75b3df"},
+    "ace.basis": {"fetch_kib": 394950.7, "write_kib": 1128297.9, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
-    "ace.force": {"fetch_kib": 976035.0, "write_kib": 2774930.7, "units": 1137181,
+        "source_sha256": "5f9370f6cb936839c61624ac7032b0f06b53118e2e38365273338e5a8f75b3df"},
+    "ace.force": {"fetch_kib": 976031.9, "write_kib": 2774215.6, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
-    "ace.backproject": {"fetch_kib": 555311.9, "write_kib": 1110562.5, "units": 1137181,
+        "source_sha256": "5f9370f6cb936839c61624ac7032b0f06b53118e2e38365273338e5a8f75b3df"},
+    "ace.backproject": {"fetch_kib": 555339.0, "write_kib": 1110562.5, "units": 1137181,
         "source": "paper_2411_03002_amd/csrc/ace.hip",
-        "source_sha256": "710c86dcb6d3cadf13a63dff32f3f785d5912abd9e64e146d1a596afe8e6ac2f"},
-    "eam.density": {"fetch_kib": 623671.1, "write_kib": 125000.0, "units": 4000000,
+        "source_sha256": "5f9370f6cb936839c61624ac7032b0f06b53118e2e38365273338e5a8f75b3df"},
+    "eam.density": {"fetch_kib": 623496.4, "write_kib": 125000.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "eam.force": {"fetch_kib": 821080.4, "write_kib": 93750.0, "units": 4000000,
+    "eam.force": {"fetch_kib": 821365.8, "write_kib": 93750.0, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/eam.hip",
         "source_sha256": "183e44649344ca6889755f53585469a4634af1bab88d6b2cf9810c9fd5ba6970"},
-    "nbr.build": {"fetch_kib": 185411.5, "write_kib": 1216116.9, "units": 4000000,
+    "nbr.build": {"fetch_kib": 185412.8, "write_kib": 1216098.9, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/neighbors.hip",
         "source_sha256": "03850caf5368f1ef36e179c1c420166396fada9283c442c89b4a770226a9453a"},
-    "prec.csp": {"fetch_kib": 1010249.8, "write_kib": 94062.5, "units": 4000000,
+    "prec.csp": {"fetch_kib": 1009092.1, "write_kib": 94062.5, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/precision.hip",
         "source_sha256": "a7812fbabcc117a32a09dbbcdac85f910fe171945d9873000a3090c270592727"},
-    "md.kick_drift": {"fetch_kib": 187627.4, "write_kib": 185642.1, "units": 4000000,
+    "md.kick_drift": {"fetch_kib": 187627.0, "write_kib": 185638.3, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/md.hip",
         "source_sha256": "8d7ab8f38bc1bd1152b97664fba70554bc73dfe7071e9989efb7c238119d3b53"},
-    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.8, "units": 4000000,
+    "blend": {"fetch_kib": 132651.0, "write_kib": 125066.9, "units": 4000000,
         "source": "paper_2411_03002_amd/csrc/blend.hip",
         "source_sha256": "bee68539ddde7cd4a46af5411dc13e285eed2822a8bc933241cbee66b16952d9"},
 }

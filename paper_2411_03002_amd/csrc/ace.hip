@@ -709,8 +709,8 @@ __global__ void __launch_bounds__(NW * 64) k_ace_products(const T* __restrict__ 
 // (lane = atom): B[k][lm] = sum_n Wp[l][n][k] Abar[n][lm], read and written tile-major
 // [tile][a][64], so every load and store of a wave is one coalesced 256-byte segment.  A
 // wave takes columns lm = wave, wave + 4, ...; a column's K adjoint values are loaded once
-// and serve its K outputs, and the weights are wave-uniform scalar loads.  The sum runs
-// over n in ascending order.
+// and serve its K outputs, which are summed in registers; the weights are staged in LDS
+// once per block.  The sum runs over n in ascending order.
 template <class T, int LMAX>
 __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ Abg, T* __restrict__ Bg,
                                                          const T* __restrict__ Wp, int K, int na) {
@@ -720,6 +720,13 @@ __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ A
   // the wave index is uniform across the wave: said so, the column's l is too and the
   // weights become scalar loads (otherwise every lane loads the same weight)
   const int t = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the weights of every l, rows padded to kMaxK (zeros), read by broadcast LDS loads
+  __shared__ T ws[(LMAX + 1) * kMaxK * kMaxK];
+  for (int e = threadIdx.x; e < (LMAX + 1) * kMaxK * kMaxK; e += 256) {
+    const int l = e / (kMaxK * kMaxK), r = e - l * kMaxK * kMaxK, nn = r / kMaxK, kk = r - nn * kMaxK;
+    ws[e] = nn < K && kk < K ? Wp[((size_t)l * K + nn) * K + kk] : T(0);
+  }
+  __syncthreads();
   const T* Ab = Abg + (size_t)blockIdx.x * na * TILE;
   T* B = Bg + (size_t)blockIdx.x * na * TILE;
   for (int lm = wv; lm < LM; lm += 4) {
@@ -728,14 +735,20 @@ __global__ void __launch_bounds__(256) k_ace_backproject(const T* __restrict__ A
     T a[kMaxK];
 #pragma unroll
     for (int nn = 0; nn < kMaxK; ++nn) a[nn] = nn < K ? Ab[(size_t)(nn * LM + lm) * TILE + t] : T(0);
-    for (int kk = 0; kk < K; ++kk) {
-      T v = T(0);
+    T v[kMaxK];
 #pragma unroll
-      for (int nn = 0; nn < kMaxK; ++nn) {
-        if (nn < K) v += *(const __attribute__((address_space(4))) T*)(Wp + ((size_t)l * K + nn) * K + kk) * a[nn];
+    for (int kk = 0; kk < kMaxK; ++kk) v[kk] = T(0);
+#pragma unroll
+    for (int nn = 0; nn < kMaxK; ++nn) {
+      if (nn < K) {
+        const T* w = ws + (l * kMaxK + nn) * kMaxK;
+#pragma unroll
+        for (int kk = 0; kk < kMaxK; ++kk) v[kk] += w[kk] * a[nn];
       }
-      B[(size_t)(kk * LM + lm) * TILE + t] = v;
     }
+#pragma unroll
+    for (int kk = 0; kk < kMaxK; ++kk)
+      if (kk < K) B[(size_t)(kk * LM + lm) * TILE + t] = v[kk];
   }
 }
 
@@ -1353,10 +1366,12 @@ __global__ void __launch_bounds__(NW * 64, G <= 3 ? 2 : 1) k_ace_adjoint(const T
   third_flush<T, LMAX, NMAX, TILE, NW, LG>(Abt, As, n_max, t, wv, lane, acc3);
 }
 
+// Clears m values of T at p with 16-byte stores (p 16-byte aligned, m * sizeof(T) a multiple
+// of 16: the adjoint's tile regions).
 template <class T>
 __global__ void k_fill_zero_t(T* __restrict__ p, long long m) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) p[i] = T(0);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m * (long long)sizeof(T) / 16) reinterpret_cast<float4*>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, long long m) {
@@ -1433,7 +1448,8 @@ apx_status ace_run(apx_ctx* ctx, const apx_atoms* atoms, const apx_nlist* nl, co
     const long long nab = n_pad * na;
     {
       ProfScope ps(ctx, "ace.zero");
-      k_fill_zero_t<T><<<blocks_for(nab, 256), 256, 0, ctx->stream>>>(sc.Ab, nab);
+      static_assert(TILE * sizeof(T) % 16 == 0, "tile regions are whole 16-byte groups");
+      k_fill_zero_t<T><<<blocks_for(nab * (long long)sizeof(T) / 16, 256), 256, 0, ctx->stream>>>(sc.Ab, nab);
       APX_LAUNCH_CHECK(ctx);
     }
     const unsigned nblk = (unsigned)((n_act + TILE - 1) / TILE);
